@@ -1,0 +1,207 @@
+/*
+ * hk.h - C ABI of the MI355X (gfx950) library for the sketched
+ * inner-product-free Krylov methods sCMRH and sLSLU of
+ *   M. Sabate Landman, A. N. Brown, J. Chung, J. G. Nagy,
+ *   "Randomized and Inner-product Free Krylov Methods for Large-scale
+ *    Inverse Problems".
+ *
+ * The library solves the linear inverse problem b = A x_true + e (Sec. 1,
+ * eq. (ip)) with A reached only through products with A (and A^T).  A solve
+ * runs k steps of the Hessenberg process with partial pivoting (square A,
+ * eq. (Hessenberg_s); "sCMRH") or of the generalized Hessenberg process
+ * (rectangular A, eq. (Hessenberg_r); "sLSLU", Algorithm 1), sketches each
+ * new column A l_j with a random embedding S2 (Sec. 2), and returns
+ *   x_k = L_k y,  y = argmin ||S2 (b - A L_k y)||^2 + lambda^2 ||S1 L_k y||^2
+ * (Sec. 3.2, eq. (sketched_LSLU); Sec. 3.3, eq. (sketched_LSLU_hybrid) and
+ * Algorithm 2), with x0 = 0.
+ *
+ * Conventions
+ *  - Every call returns an hk_status.  0 = HK_OK; HK_BREAKDOWN (1) is
+ *    informational: the Krylov subspace became invariant after k_done < k
+ *    steps (a zero pivot) and the solution was computed from the k_done
+ *    columns built; negative values are errors.  hk_last_error() returns a
+ *    thread-local message describing the last error.
+ *  - "device" pointers are HIP device allocations of the context's device
+ *    (e.g. torch tensors on that GPU); "host" pointers are ordinary memory.
+ *  - The library copies every operator input it is given (taps, CSR arrays)
+ *    and never frees or retains caller memory.  Handles are opaque and are
+ *    destroyed exactly once by the caller.
+ *  - All device work of a context is ordered on the context's HIP stream;
+ *    hk_solve_run is asynchronous.  Getters wait for the solve to finish.
+ *  - Indices (pivots) are 0-based row indices of the original problem.
+ *  - b and x are stored in the operator's storage type (hk_dtype), the
+ *    Krylov bases in hk_params.basis_dtype.  All arithmetic is done in FP64;
+ *    FP32 storage halves the bytes streamed.
+ */
+#ifndef HK_H
+#define HK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HK_ABI_VERSION 1
+
+typedef int32_t hk_status;
+enum {
+    HK_OK = 0,
+    HK_BREAKDOWN = 1,      /* zero pivot: k_done < k columns were built */
+    HK_EINVAL = -1,        /* invalid argument */
+    HK_ENOMEM = -2,        /* device or host allocation failed */
+    HK_EDEVICE = -3,       /* HIP runtime error or device-side abort */
+    HK_ENUMERIC = -4,      /* NaN/Inf in the data, or a rank-deficient sketched problem */
+    HK_EUNSUPPORTED = -5   /* valid request outside what this build implements */
+};
+
+typedef int32_t hk_dtype;
+enum { HK_F64 = 0, HK_F32 = 1 };
+
+typedef int32_t hk_bc;     /* boundary condition of the blur */
+enum { HK_BC_ZERO = 0, HK_BC_REFLECT = 1 };
+
+typedef int32_t hk_sketch;
+enum { HK_SKETCH_GAUSSIAN = 0, HK_SKETCH_SPARSE_SIGN = 1 };
+
+typedef int32_t hk_method;
+enum { HK_METHOD_AUTO = 0, HK_METHOD_HESSENBERG = 1, HK_METHOD_CHANGING_HESSENBERG = 2 };
+
+enum { HK_FLAG_TRACE = 1 };
+
+typedef struct hk_context hk_context;
+typedef struct hk_op hk_op;
+typedef struct hk_solve hk_solve;
+
+/* ABI version (HK_ABI_VERSION) and the thread-local last error message. */
+int32_t hk_abi_version(void);
+const char* hk_last_error(void);
+
+/* Create a context on HIP device `device`, ordering work on `stream`
+ * (a hipStream_t, or NULL for the default stream).  The stream is borrowed:
+ * the caller keeps it alive for the context's lifetime. */
+hk_status hk_context_create(int32_t device, void* stream, hk_context** out);
+hk_status hk_context_destroy(hk_context* ctx);
+
+/* Blur operator on an ny x nx image stored row-major (index y*nx + x), the
+ * blur model of the deblurring experiment (Sec. 4.1):
+ *   (A u)(y, x) = sum_{a,b=-r..r} taps_y[a+r] taps_x[b+r] u(y+a, x+b),
+ * a 2-D correlation with the separable PSF taps_y (x) taps_x.  Pixels outside
+ * the image are 0 (HK_BC_ZERO) or the half-sample mirror image
+ * u(-1) = u(0), u(N) = u(N-1) (HK_BC_REFLECT).  taps_y / taps_x: host arrays
+ * of 2r+1 doubles, copied.  dt: storage type of vectors used with the op.
+ * Square (m = n = ny*nx); only the forward product is provided, so blur
+ * operators take the square (Hessenberg) method. */
+hk_status hk_op_create_blur(hk_context* ctx, int64_t ny, int64_t nx, const double* taps_y,
+                            const double* taps_x, int32_t radius, hk_bc bc, hk_dtype dt,
+                            hk_op** out);
+
+/* Convenience: Gaussian PSF, taps g(a) ~ exp(-a^2 / (2 sigma^2)) normalised to
+ * sum 1 in each direction. */
+hk_status hk_op_create_gaussian_blur(hk_context* ctx, int64_t ny, int64_t nx, double sigma,
+                                     int32_t radius, hk_bc bc, hk_dtype dt, hk_op** out);
+
+/* Sparse operator A (m x n) in CSR form: host arrays rowptr[m+1] (int64,
+ * rowptr[0] = 0, nondecreasing, rowptr[m] = nnz), col[nnz] (int32, in
+ * [0, n)), val[nnz] of type dt.  All copied.  The library also builds A^T
+ * so that both products (Algorithm 1) are available. */
+hk_status hk_op_create_csr(hk_context* ctx, int64_t m, int64_t n, int64_t nnz,
+                           const int64_t* rowptr, const int32_t* col, const void* val,
+                           hk_dtype dt, hk_op** out);
+
+hk_status hk_op_shape(const hk_op* op, int64_t* m, int64_t* n);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1, CSR only): device
+ * vectors of the operator's dtype, lengths n -> m (or m -> n).  FP64
+ * accumulation.  Stream-ordered, asynchronous. */
+hk_status hk_op_apply(hk_op* op, int32_t transpose, const void* x_dev, void* y_dev);
+hk_status hk_op_destroy(hk_op* op);
+
+/* Solve parameters.
+ *   k       number of Hessenberg steps (basis size), 1 <= k <= min(m, n), k <= 255
+ *   s       sketch rows (the embedding dimension l of Sec. 2), s >= k + 1
+ *   lambda  Tikhonov parameter >= 0; it enters squared (Sec. 3.3)
+ *   sketch  Gaussian (entries N(0, 1/s), Sec. 2) or sparse sign (zeta nonzeros
+ *           of value +-1/sqrt(zeta) per column, one in each of zeta row blocks)
+ *   zeta    nonzeros per column of the sparse-sign embedding, 1 <= zeta <= s
+ *   seed    64-bit key of the Philox4x32-10 generator that defines S1, S2
+ *   method  AUTO: Hessenberg (sCMRH) for square operators, generalized
+ *           (sLSLU) otherwise
+ *   basis_dtype  storage type of the Krylov bases L (and D): HK_F64, or
+ *           HK_F32 when the operator is FP32 as well (halves the basis bytes;
+ *           all arithmetic stays FP64).  FP64 bases with an FP32 operator
+ *           are allowed.  A zero-initialised struct selects HK_F64.
+ *   flags   0, or HK_FLAG_TRACE: workgroup 0 of the basis kernel records a
+ *           wall-clock timestamp before and after every grid barrier
+ *           (read them with hk_solve_get_trace) */
+typedef struct {
+    int32_t k;
+    int32_t s;
+    double lambda;
+    hk_sketch sketch;
+    int32_t zeta;
+    uint64_t seed;
+    hk_method method;
+    hk_dtype basis_dtype;
+    uint32_t flags;
+} hk_params;
+
+/* Device workspace a solve of `op` with `params` holds (bases, Hessenberg
+ * matrices, sketches and partial sums), for admission control. */
+hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* params, size_t* bytes);
+
+/* Create a solve: validates the parameters and allocates its workspace.
+ * The solve can be run many times (each run overwrites its results). */
+hk_status hk_solve_create(hk_op* op, const hk_params* params, hk_solve** out);
+
+/* Run: enqueue the whole solve on the context stream and return at once.
+ * b_dev: device vector, m elements of the op's dtype (read during the run).
+ * x_dev: device vector, n elements of the op's dtype (written during the run). */
+hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev);
+
+/* Wait for the last run.  Returns HK_OK, HK_BREAKDOWN, or an error. */
+hk_status hk_solve_wait(hk_solve* sv);
+
+/* Results of the last run (each call waits for it first).
+ *   k_done      number of basis columns used (k, or fewer after breakdown)
+ *   H           host, (k+1) x k FP64 column-major upper Hessenberg H_{k+1,k}
+ *   W           host, k x k FP64 column-major upper triangular (sLSLU), or NULL
+ *   t           host, k+1 int64 pivots of L (sCMRH) or of D (sLSLU); -1 unused
+ *   g           host, k int64 pivots of L (sLSLU), or NULL
+ *   res         host, k FP64: res[j] = minimised sketched objective
+ *               (||S2(b - A L y)||^2 + lambda^2 ||S1 L y||^2)^(1/2) using the
+ *               first j+1 columns; entries past k_done are 0
+ *   Z, F, c     host: S2 A L_k (s x k), S1 L_k (s x k, zero if lambda = 0),
+ *               S2 b (s), FP64 column-major
+ *   basis       which = 0: L (n x (k+1)), which = 1: D (m x (k+1), sLSLU),
+ *               copied to a device buffer of basis_dtype, column-major */
+hk_status hk_solve_info(hk_solve* sv, int32_t* k_done);
+hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W);
+hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g);
+hk_status hk_solve_get_residuals(hk_solve* sv, double* res);
+hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c);
+hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev);
+
+/* Device-side duration of the last run's Hessenberg kernel and of the whole
+ * run, in milliseconds (HIP events on the context stream). */
+hk_status hk_solve_timing(hk_solve* sv, double* iterate_ms, double* total_ms);
+
+/* The same for each of the most recent runs (up to 256 are kept, oldest
+ * first): writes min(max_runs, runs kept) entries to iterate_ms / total_ms
+ * (host arrays) and their number to *n.  Waits for the newest run. */
+hk_status hk_solve_timing_history(hk_solve* sv, int32_t max_runs, double* iterate_ms,
+                                  double* total_ms, int32_t* n);
+
+/* Barrier timestamps of the last run (needs HK_FLAG_TRACE): ticks[2e] when
+ * workgroup 0 reached grid barrier e, ticks[2e+1] when it was released.
+ * Writes min(max, recorded) values, their count to *n and the tick length in
+ * nanoseconds to *tick_ns. */
+hk_status hk_solve_get_trace(hk_solve* sv, int32_t max, uint64_t* ticks, int32_t* n, double* tick_ns);
+
+hk_status hk_solve_destroy(hk_solve* sv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HK_H */

@@ -1,0 +1,414 @@
+"""Python binding of the gfx950 library ``libhk.so`` (C ABI in ``include/hk.h``).
+
+Sketched inner-product-free Krylov solvers (sCMRH for square operators,
+sLSLU for rectangular ones) for linear inverse problems b = A x + e.
+
+The binding only marshals arguments: every step of a solve runs in the HIP
+kernels of ``libhk.so``.  PyTorch provides device memory and the stream.
+There is no CPU fallback: if the library is not built, importing works but
+every call raises.
+
+Functions named like the C ABI (``hk_context_create``, ``hk_solve_run``, ...)
+map one to one onto it; ``Context``, ``Operator`` and ``Solve`` wrap them
+for use with torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhk.so")
+
+HK_OK, HK_BREAKDOWN = 0, 1
+HK_EINVAL, HK_ENOMEM, HK_EDEVICE, HK_ENUMERIC, HK_EUNSUPPORTED = -1, -2, -3, -4, -5
+HK_F64, HK_F32 = 0, 1
+HK_BC_ZERO, HK_BC_REFLECT = 0, 1
+HK_SKETCH_GAUSSIAN, HK_SKETCH_SPARSE_SIGN = 0, 1
+HK_METHOD_AUTO, HK_METHOD_HESSENBERG, HK_METHOD_CHANGING_HESSENBERG = 0, 1, 2
+HK_FLAG_TRACE = 1
+
+# names exported by the C ABI (checked against the header by the tests)
+ABI_FUNCTIONS = (
+    "hk_abi_version", "hk_last_error", "hk_context_create", "hk_context_destroy",
+    "hk_op_create_blur", "hk_op_create_gaussian_blur", "hk_op_create_csr", "hk_op_shape",
+    "hk_op_apply", "hk_op_destroy", "hk_solve_workspace_bytes", "hk_solve_create",
+    "hk_solve_run", "hk_solve_wait", "hk_solve_info", "hk_solve_get_hessenberg",
+    "hk_solve_get_pivots", "hk_solve_get_residuals", "hk_solve_get_sketches",
+    "hk_solve_get_basis", "hk_solve_timing", "hk_solve_timing_history", "hk_solve_get_trace",
+    "hk_solve_destroy",
+)
+
+
+class HKError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hk status {status}: {msg}")
+        self.status = status
+
+
+class hk_params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("s", C.c_int32), ("lambda_", C.c_double),
+                ("sketch", C.c_int32), ("zeta", C.c_int32), ("seed", C.c_uint64),
+                ("method", C.c_int32), ("basis_dtype", C.c_int32), ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2502_02721_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_int32
+        pp = C.POINTER(C.c_void_p)
+        sig = {
+            "hk_abi_version": ([], i32),
+            "hk_last_error": ([], C.c_char_p),
+            "hk_context_create": ([i32, vp, pp], st),
+            "hk_context_destroy": ([vp], st),
+            "hk_op_create_blur": ([vp, i64, i64, vp, vp, i32, i32, i32, pp], st),
+            "hk_op_create_gaussian_blur": ([vp, i64, i64, C.c_double, i32, i32, i32, pp], st),
+            "hk_op_create_csr": ([vp, i64, i64, i64, vp, vp, vp, i32, pp], st),
+            "hk_op_shape": ([vp, C.POINTER(i64), C.POINTER(i64)], st),
+            "hk_op_apply": ([vp, i32, vp, vp], st),
+            "hk_op_destroy": ([vp], st),
+            "hk_solve_workspace_bytes": ([vp, C.POINTER(hk_params), C.POINTER(C.c_size_t)], st),
+            "hk_solve_create": ([vp, C.POINTER(hk_params), pp], st),
+            "hk_solve_run": ([vp, vp, vp], st),
+            "hk_solve_wait": ([vp], st),
+            "hk_solve_info": ([vp, C.POINTER(i32)], st),
+            "hk_solve_get_hessenberg": ([vp, vp, vp], st),
+            "hk_solve_get_pivots": ([vp, vp, vp], st),
+            "hk_solve_get_residuals": ([vp, vp], st),
+            "hk_solve_get_sketches": ([vp, vp, vp, vp], st),
+            "hk_solve_get_basis": ([vp, i32, vp], st),
+            "hk_solve_timing": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double)], st),
+            "hk_solve_timing_history": ([vp, i32, vp, vp, C.POINTER(i32)], st),
+            "hk_solve_get_trace": ([vp, i32, vp, C.POINTER(i32), C.POINTER(C.c_double)], st),
+            "hk_solve_destroy": ([vp], st),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow_breakdown: bool = False) -> int:
+    if status < 0 or (status == HK_BREAKDOWN and not allow_breakdown):
+        raise HKError(status, lib().hk_last_error().decode())
+    return status
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+# ---------------------------------------------------------------- raw ABI
+def hk_abi_version() -> int:
+    return lib().hk_abi_version()
+
+
+def hk_last_error() -> str:
+    return lib().hk_last_error().decode()
+
+
+def hk_context_create(device: int, stream: int) -> int:
+    h = C.c_void_p()
+    _check(lib().hk_context_create(device, C.c_void_p(stream), C.byref(h)))
+    return h.value
+
+
+def hk_context_destroy(ctx: int) -> None:
+    _check(lib().hk_context_destroy(C.c_void_p(ctx)))
+
+
+def hk_op_create_blur(ctx, ny, nx, taps_y, taps_x, radius, bc, dtype) -> int:
+    ty = np.ascontiguousarray(taps_y, dtype=np.float64)
+    tx = np.ascontiguousarray(taps_x, dtype=np.float64)
+    if ty.size != 2 * radius + 1 or tx.size != 2 * radius + 1:
+        raise ValueError("taps must have 2*radius+1 entries")
+    h = C.c_void_p()
+    _check(lib().hk_op_create_blur(C.c_void_p(ctx), ny, nx, _np_ptr(ty), _np_ptr(tx), radius, bc,
+                                   dtype, C.byref(h)))
+    return h.value
+
+
+def hk_op_create_gaussian_blur(ctx, ny, nx, sigma, radius, bc, dtype) -> int:
+    h = C.c_void_p()
+    _check(lib().hk_op_create_gaussian_blur(C.c_void_p(ctx), ny, nx, sigma, radius, bc, dtype,
+                                            C.byref(h)))
+    return h.value
+
+
+def hk_op_create_csr(ctx, m, n, rowptr, col, val, dtype) -> int:
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    vl = np.ascontiguousarray(val, dtype=np.float64 if dtype == HK_F64 else np.float32)
+    h = C.c_void_p()
+    _check(lib().hk_op_create_csr(C.c_void_p(ctx), m, n, int(rp[-1]), _np_ptr(rp), _np_ptr(cl),
+                                  _np_ptr(vl), dtype, C.byref(h)))
+    return h.value
+
+
+def hk_op_shape(op) -> tuple:
+    m, n = C.c_int64(), C.c_int64()
+    _check(lib().hk_op_shape(C.c_void_p(op), C.byref(m), C.byref(n)))
+    return m.value, n.value
+
+
+def hk_op_apply(op, transpose: int, x_ptr: int, y_ptr: int) -> None:
+    _check(lib().hk_op_apply(C.c_void_p(op), transpose, C.c_void_p(x_ptr), C.c_void_p(y_ptr)))
+
+
+def hk_op_destroy(op) -> None:
+    _check(lib().hk_op_destroy(C.c_void_p(op)))
+
+
+def make_params(k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0, method=HK_METHOD_AUTO,
+                basis_dtype=HK_F64, flags=0) -> hk_params:
+    return hk_params(k=k, s=s, lambda_=lam, sketch=sketch, zeta=zeta, seed=seed, method=method,
+                     basis_dtype=basis_dtype, flags=flags)
+
+
+def hk_solve_workspace_bytes(op, params: hk_params) -> int:
+    b = C.c_size_t()
+    _check(lib().hk_solve_workspace_bytes(C.c_void_p(op), C.byref(params), C.byref(b)))
+    return b.value
+
+
+def hk_solve_create(op, params: hk_params) -> int:
+    h = C.c_void_p()
+    _check(lib().hk_solve_create(C.c_void_p(op), C.byref(params), C.byref(h)))
+    return h.value
+
+
+def hk_solve_run(sv, b_ptr: int, x_ptr: int) -> None:
+    _check(lib().hk_solve_run(C.c_void_p(sv), C.c_void_p(b_ptr), C.c_void_p(x_ptr)))
+
+
+def hk_solve_wait(sv) -> int:
+    return _check(lib().hk_solve_wait(C.c_void_p(sv)), allow_breakdown=True)
+
+
+def hk_solve_info(sv) -> int:
+    k = C.c_int32()
+    _check(lib().hk_solve_info(C.c_void_p(sv), C.byref(k)), allow_breakdown=True)
+    return k.value
+
+
+def hk_solve_get_hessenberg(sv, k: int, rect: bool):
+    H = np.zeros((k + 1, k), order="F")
+    W = np.zeros((k, k), order="F") if rect else None
+    _check(lib().hk_solve_get_hessenberg(C.c_void_p(sv), _np_ptr(H), _np_ptr(W)))
+    return H, W
+
+
+def hk_solve_get_pivots(sv, k: int, rect: bool):
+    t = np.zeros(k + 1, dtype=np.int64)
+    g = np.zeros(k, dtype=np.int64) if rect else None
+    _check(lib().hk_solve_get_pivots(C.c_void_p(sv), _np_ptr(t), _np_ptr(g)))
+    return t, g
+
+
+def hk_solve_get_residuals(sv, k: int) -> np.ndarray:
+    r = np.zeros(k)
+    _check(lib().hk_solve_get_residuals(C.c_void_p(sv), _np_ptr(r)))
+    return r
+
+
+def hk_solve_get_sketches(sv, s: int, k: int):
+    Z = np.zeros((s, k), order="F"); F = np.zeros((s, k), order="F"); c = np.zeros(s)
+    _check(lib().hk_solve_get_sketches(C.c_void_p(sv), _np_ptr(Z), _np_ptr(F), _np_ptr(c)))
+    return Z, F, c
+
+
+def hk_solve_get_basis(sv, which: int, dst_ptr: int) -> None:
+    _check(lib().hk_solve_get_basis(C.c_void_p(sv), which, C.c_void_p(dst_ptr)))
+
+
+def hk_solve_timing(sv):
+    a, b = C.c_double(), C.c_double()
+    _check(lib().hk_solve_timing(C.c_void_p(sv), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def hk_solve_timing_history(sv, max_runs: int):
+    it = np.zeros(max_runs); tot = np.zeros(max_runs); n = C.c_int32()
+    _check(lib().hk_solve_timing_history(C.c_void_p(sv), max_runs, _np_ptr(it), _np_ptr(tot), C.byref(n)))
+    return it[: n.value], tot[: n.value]
+
+
+def hk_solve_get_trace(sv, max_ticks: int = 1 << 16):
+    t = np.zeros(max_ticks, dtype=np.uint64); n = C.c_int32(); ns = C.c_double()
+    _check(lib().hk_solve_get_trace(C.c_void_p(sv), max_ticks, _np_ptr(t), C.byref(n), C.byref(ns)))
+    return t[: n.value], ns.value
+
+
+def hk_solve_destroy(sv) -> None:
+    _check(lib().hk_solve_destroy(C.c_void_p(sv)))
+
+
+# ---------------------------------------------------------------- torch wrappers
+def _torch():
+    import torch
+    return torch
+
+
+_DT = {HK_F64: "float64", HK_F32: "float32"}
+
+
+class Context:
+    """A device and a stream (default: torch's current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        self.handle = hk_context_create(device, stream.cuda_stream)
+
+    def close(self):
+        if self.handle:
+            hk_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    def __init__(self, ctx: Context, handle: int, dtype: int):
+        self.ctx, self.handle, self.dtype = ctx, handle, dtype
+        self.m, self.n = hk_op_shape(handle)
+
+    @classmethod
+    def blur(cls, ctx, ny, nx, taps_y, taps_x, radius, bc, dtype):
+        return cls(ctx, hk_op_create_blur(ctx.handle, ny, nx, taps_y, taps_x, radius, bc, dtype), dtype)
+
+    @classmethod
+    def gaussian_blur(cls, ctx, ny, nx, sigma, radius, bc, dtype):
+        return cls(ctx, hk_op_create_gaussian_blur(ctx.handle, ny, nx, sigma, radius, bc, dtype), dtype)
+
+    @classmethod
+    def csr(cls, ctx, m, n, rowptr, col, val, dtype):
+        return cls(ctx, hk_op_create_csr(ctx.handle, m, n, rowptr, col, val, dtype), dtype)
+
+    def torch_dtype(self):
+        return getattr(_torch(), _DT[self.dtype])
+
+    def _vec(self, t, length, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+        if t.dtype != self.torch_dtype() or t.numel() != length or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {_DT[self.dtype]} tensor of {length} elements")
+        return t
+
+    def apply(self, x, transpose: bool = False, out=None):
+        torch = _torch()
+        lin, lout = (self.m, self.n) if transpose else (self.n, self.m)
+        self._vec(x, lin, "x")
+        if out is None:
+            out = torch.empty(lout, dtype=self.torch_dtype(), device=x.device)
+        self._vec(out, lout, "out")
+        hk_op_apply(self.handle, 1 if transpose else 0, x.data_ptr(), out.data_ptr())
+        return out
+
+    def close(self):
+        if self.handle:
+            hk_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solve:
+    """A solve of one operator with fixed parameters; run() may be called repeatedly."""
+
+    def __init__(self, op: Operator, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
+                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0):
+        self.op = op
+        if basis_dtype is None:
+            basis_dtype = op.dtype
+        self.basis_dtype = basis_dtype
+        self.params = make_params(k, s, lam, sketch, zeta, seed, method, basis_dtype, flags)
+        self.k, self.s = k, s
+        self.rect = (method == HK_METHOD_CHANGING_HESSENBERG) or (method == HK_METHOD_AUTO and op.m != op.n)
+        self.handle = hk_solve_create(op.handle, self.params)
+
+    def workspace_bytes(self) -> int:
+        return hk_solve_workspace_bytes(self.op.handle, self.params)
+
+    def run(self, b, x=None):
+        torch = _torch()
+        self.op._vec(b, self.op.m, "b")
+        if x is None:
+            x = torch.empty(self.op.n, dtype=self.op.torch_dtype(), device=b.device)
+        self.op._vec(x, self.op.n, "x")
+        hk_solve_run(self.handle, b.data_ptr(), x.data_ptr())
+        self._b, self._x = b, x   # keep alive until the run completes
+        return x
+
+    def wait(self) -> int:
+        return hk_solve_wait(self.handle)
+
+    def k_done(self) -> int:
+        return hk_solve_info(self.handle)
+
+    def hessenberg(self):
+        return hk_solve_get_hessenberg(self.handle, self.k, self.rect)
+
+    def pivots(self):
+        return hk_solve_get_pivots(self.handle, self.k, self.rect)
+
+    def residuals(self):
+        return hk_solve_get_residuals(self.handle, self.k)
+
+    def sketches(self):
+        return hk_solve_get_sketches(self.handle, self.s, self.k)
+
+    def basis(self, which: int = 0):
+        torch = _torch()
+        length = self.op.n if which == 0 else self.op.m
+        tdt = getattr(torch, _DT[self.basis_dtype])
+        out = torch.empty((self.k + 1, length), dtype=tdt, device=f"cuda:{self.op.ctx.device}")
+        hk_solve_get_basis(self.handle, which, out.data_ptr())
+        return out   # row i = basis vector i
+
+    def timing(self):
+        return hk_solve_timing(self.handle)
+
+    def trace(self):
+        """Per-barrier (arrive, release) timestamps of workgroup 0, in ns."""
+        t, ns = hk_solve_get_trace(self.handle)
+        return t.astype(np.float64) * ns
+
+    def timing_history(self, max_runs: int = 256):
+        return hk_solve_timing_history(self.handle, max_runs)
+
+    def close(self):
+        if self.handle:
+            hk_solve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,376 @@
+// Persistent single-barrier Hessenberg iteration for blur operators (square
+// A, the Hessenberg process with partial pivoting of Sec. 3.1,
+// eq. (Hessenberg_s), sketched as in Sec. 3.2).
+//
+// Each step j is one phase between two grid barriers:
+//   1. global argmax of v_j (partials of the previous phase): pivot p_j and
+//      eta_j = v_j(p_j); l_j = v_j / eta_j is kept as the stored,
+//      unnormalised v_j with the FP64 scale s_j = 1 / eta_j;
+//   2. reduce last step's sketch partials: z_{j-1} = S2 A l_{j-1},
+//      f_{j-1} = S1 l_{j-1};
+//   3. coefficients: row j of the pivot block (P(j, i) = l_i(p_j), gathered
+//      from the stored basis) and u(p_i) = (A l_j)(p_i) for all pivots:
+//      window sums that the tiles owning each pivot's window left in the
+//      previous phase, plus one redundant 31x31-type stencil at p_j; then
+//      h = P^{-1} u(p) by forward substitution (identical in every
+//      workgroup);
+//   4. on the tile: u = A l_j (separable blur of v_j with an LDS halo),
+//      z_j partials; v_{j+1} = u - sum_i h_i l_i streamed over the stored
+//      basis; exact zeros at pivot rows; argmax partial; store v_{j+1};
+//      window sums of A v_{j+1} at the pivots whose window meets the tile;
+//      f_j partials.
+// No inner product is formed; the only global synchronisation per step is
+// the grid barrier.
+#pragma once
+#include "hk_device.hpp"
+
+namespace hk {
+
+struct WBox {
+    int ylo, yhi, xlo, xhi;     // source pixels of the pivot's stencil window
+    int tyl, tyh, txl, txh;     // tiles that hold them
+};
+
+__device__ __forceinline__ WBox wbox(int p, int ny, int nx, int r, int TY, int TX)
+{
+    const int py = p / nx, px = p - py * nx;
+    WBox b;
+    b.ylo = max(0, py - r); b.yhi = min(ny - 1, py + r);
+    b.xlo = max(0, px - r); b.xhi = min(nx - 1, px + r);
+    b.tyl = b.ylo / TY; b.tyh = b.yhi / TY;
+    b.txl = b.xlo / TX; b.txh = b.xhi / TX;
+    return b;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) t += red[w];
+    return t;
+}
+
+// (A v)(p) for the stored vector v (global), every workgroup the same way.
+template <typename TB>
+__device__ double stencil_at(const TB* __restrict__ v, int p, int ny, int nx, int r, int bc,
+                             const double* tyl, const double* txl, double* red)
+{
+    const int py = p / nx, px = p - py * nx;
+    const int w = 2 * r + 1;
+    constexpr int SB = 4;
+    double acc = 0.0;
+    for (int o0 = 0; o0 < w * w; o0 += SB * NT) {
+        TB val[SB];
+        double wgt[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int o = o0 + u * NT + (int)threadIdx.x;
+            const int oc = o < w * w ? o : 0;
+            const int a = oc / w, b = oc - a * w;
+            const int y = bc_map(py + a - r, ny, bc), x = bc_map(px + b - r, nx, bc);
+            const bool in = o < w * w && y >= 0 && x >= 0;
+            val[u] = v[in ? y * nx + x : 0];
+            wgt[u] = in ? tyl[a] * txl[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) acc = fma(wgt[u], (double)val[u], acc);
+    }
+    return block_sum(acc, red);
+}
+
+template <typename TB, typename TO, int SK, int EPT>
+__global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_cnt;
+    __shared__ double s_red[NWAVE];
+    double* h_l = (double*)(smem + a.lds_h);
+    double* hs_l = (double*)(smem + a.lds_hs);
+    double* sc_l = (double*)(smem + a.lds_scale);            // s_j = 1 / eta_j
+    double* scf_l = sc_l + (KMAX + 1);                       // fixed-point scale of f_j
+    double* wt = (double*)(smem + a.lds_w);
+    unsigned char* sk = smem + a.lds_sk;
+    TB* stage = (TB*)(smem + a.lds_stage);
+    double* vert = (double*)(smem + a.lds_vert);
+    double* taps = (double*)(smem + a.lds_taps);
+    TB* Pl = (TB*)(smem + a.lds_pD);
+    double* wred = (double*)(smem + a.lds_wred);
+    int* pivs = (int*)(smem + a.lds_pl_n);       // all pivots found so far
+    int* wlist = (int*)(smem + a.lds_pc_n);      // pivots whose window meets this tile
+    // sparse-sign tables of S2 and S1 for this tile's elements (if they fit)
+    unsigned short* tab2 = a.lds_skt ? (unsigned short*)(smem + a.lds_skt) : nullptr;
+    unsigned short* tab1 = tab2 ? tab2 + (size_t)a.spm.TY * a.spm.TX * a.zeta : nullptr;
+    __shared__ int s_nw;                          // length of wlist
+
+    const int G = a.G;
+    const int tile = tile_of_block(G, a.xcd_map);
+    const int k = a.k;
+    const int kp1 = k + 1;
+    const int r = a.r, ny = a.ny, nx = a.nx, TY = a.spm.TY, TX = a.spm.TX;
+    const int tw = 2 * r + 1;
+    Ctl* ctl = a.ctl;
+    BarState bs;
+
+    PivState pm{(int*)(smem + a.lds_pl_m), (int*)(smem + a.lds_pc_m), (unsigned*)(smem + a.lds_bm_m), &s_cnt};
+    const Tile tm = tile_info(a.spm, tile);
+    const int tyi = tile / a.spm.ntx, txi = tile - tyi * a.spm.ntx;
+
+    for (int q = threadIdx.x; q < (NT * EPT + 31) / 32; q += NT) pm.bits[q] = 0u;
+    if (threadIdx.x == 0) { s_cnt = 0; s_nw = 0; }
+    for (int q = threadIdx.x; q < tw; q += NT) {
+        taps[q] = a.taps_y[q];
+        taps[tw + q] = a.taps_x[q];
+    }
+    const double* tyl = taps;
+    const double* txl = taps + tw;
+    if constexpr (SK == SK_SPARSE) {
+        if (tab2) {
+            sketch_sparse_table(a.spm, tm, a.s, a.zeta, 2u, a.seed_lo, a.seed_hi, tab2);
+            if (a.lam > 0.0) sketch_sparse_table(a.spm, tm, a.s, a.zeta, 1u, a.seed_lo, a.seed_hi, tab1);
+        }
+    }
+
+    int gm[EPT];
+    unsigned vm = 0u;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        int g = 0;
+        if (elem_global(a.spm, tm, threadIdx.x + i * NT, g)) vm |= 1u << i; else g = 0;
+        gm[i] = g;
+    }
+    TB* V = (TB*)a.L;
+    const long long ld = a.ldl;
+    const TO* bvec = (const TO*)a.b;
+    const double inv_sk = (SK == SK_SPARSE) ? 1.0 / sqrt((double)a.zeta) : 1.0 / sqrt((double)a.s);
+    const long long GS = (long long)G * a.s;
+
+    // sub-phase timestamps of workgroup 0 (tracing only): after the barrier
+    // timestamps, 16 slots per step
+    unsigned long long* marks = a.trace ? a.trace + 2 * (kp1 + 2) : nullptr;
+    auto mark = [&](int j, int id) {
+        if (marks && tile == 0 && threadIdx.x == 0 && (2 * (kp1 + 2) + j * 16 + id) < a.trace_cap)
+            marks[j * 16 + id] = wall_clock64();
+    };
+    auto finish = [&](int k_done, int status, int nt) {
+        if (tile == 0 && threadIdx.x == 0) {
+            ctl->k_done = k_done;
+            ctl->nt = nt;
+            ctl->ng = 0;
+            if (ctl->status == 0) ctl->status = status;
+        }
+    };
+    auto fail = [&](int status) {
+        if (tile == 0 && threadIdx.x == 0) ctl->status = status;
+    };
+
+    if (!hbar_init(ctl, bs, (unsigned)G, a.timeout_ticks)) { fail(-3); return; }
+
+    // ---- setup: v_0 = b (stored), argmax partial of b
+    {
+        double acc[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const TO bv = bvec[gm[i]];
+            acc[i] = ((vm >> i) & 1u) ? (double)bv : 0.0;
+            if ((vm >> i) & 1u) V[gm[i]] = (TB)bv;
+        }
+        tile_argmax<EPT>(acc, gm, vm, a.amv + G, a.ami + G, tile);   // read as "previous" by step 0
+    }
+    if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+    double scc = 1.0;
+    for (int j = 0; j <= k; ++j) {
+        const int par = j & 1;            // buffers written in this phase
+        const int prv = par ^ 1;          // buffers written in the previous phase
+        // ---- 1. pivot p_j and eta_j = v_j(p_j)
+        double eta;
+        int p;
+        mark(j, 0);
+        global_argmax(a.amv + prv * G, a.ami + prv * G, 0, G, eta, p);
+        mark(j, 1);
+        if (p == -2) { fail(-4); return; }
+        const bool brk = (eta == 0.0) || (j >= a.n);
+        // ---- 2. sketches of the previous column
+        if (j == 1) reduce_partials<SK>(a, a.cpart, (SK == SK_SPARSE) ? inv_sk / scc : inv_sk, tile, a.c);
+        if (j >= 1) {
+            const double sprev = sc_l[j - 1];
+            reduce_partials<SK>(a, a.zpart + prv * GS, (SK == SK_SPARSE) ? inv_sk / a.scz : inv_sk, tile,
+                                a.Z + (long long)(j - 1) * a.s);
+            if (a.lam > 0.0) {
+                const double scf = scf_l[j - 1];
+                reduce_partials<SK>(a, a.fpart + prv * GS,
+                                    ((SK == SK_SPARSE) ? inv_sk / scf : inv_sk) * sprev, tile,
+                                    a.F + (long long)(j - 1) * a.s);
+            }
+        }
+        mark(j, 2);
+        if (brk) {
+            if (tile == 0 && threadIdx.x == 0 && j >= 1) a.H[(long long)(j - 1) * kp1 + j] = 0.0;
+            if (j == 0) finish(0, 1, 0);
+            else finish(j, (j < k) ? 1 : 0, j);
+            return;
+        }
+        const double sj = 1.0 / eta;
+        // |v_j| <= |eta_j|: fixed-point scale of the S1 v_j partial sums
+        const double scf_j = fx_scale((double)a.n * fabs(eta) * 1.000001);
+        if (threadIdx.x == 0) {
+            sc_l[j] = sj; scf_l[j] = scf_j; pivs[j] = p;
+            const WBox bx = wbox(p, ny, nx, r, TY, TX);
+            if (tyi >= bx.tyl && tyi <= bx.tyh && txi >= bx.txl && txi <= bx.txh) wlist[s_nw++] = j;
+        }
+        if (tile == 0 && threadIdx.x == 0) {
+            a.scale[j] = sj;
+            a.tp[j] = p;
+            if (j >= 1) a.H[(long long)(j - 1) * kp1 + j] = eta;
+        }
+        if (j == k) { finish(k, 0, k + 1); return; }
+        __syncthreads();
+        // ---- 3. coefficients
+        {
+            int ot, oe;
+            owner_of(a.spm, p, ot, oe);
+            if (ot == tile && threadIdx.x == 0) {
+                const int c = *pm.count;
+                pm.list_e[c] = oe;
+                pm.list_c[c] = j;
+                *pm.count = c + 1;
+                pm.bits[oe >> 5] |= 1u << (oe & 31);
+            }
+        }
+        for (int c = threadIdx.x; c < j; c += NT)            // P(j, c) = l_c(p_j)
+            Pl[packed_col(c, k) + (j - c - 1)] = (TB)(sc_l[c] * (double)V[(long long)c * ld + p]);
+        if (j == 0) scc = fx_scale((double)a.m * fabs(eta) * 1.000001);
+        mark(j, 3);
+        // u(p_i) for i < j from the window partials of A v_j, u(p_j) directly
+        double* pv = wred;                                   // pv[0..j]
+        double* slotv = wred + kp1;                          // partials, [i * nslot + q]
+        const double* wpp = a.wpart + (long long)prv * kp1 * a.nslot;
+        {
+            constexpr int SB = 8;
+            const int tot = j * a.nslot;
+            for (int q0 = 0; q0 < tot; q0 += SB * NT) {
+                double vv[SB];
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    const int q = q0 + u * NT + (int)threadIdx.x;
+                    vv[u] = wpp[q < tot ? q : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    const int q = q0 + u * NT + (int)threadIdx.x;
+                    if (q < tot) slotv[q] = vv[u];
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < j; i += NT) {
+            const WBox bx = wbox(pivs[i], ny, nx, r, TY, TX);
+            double sum = 0.0;
+            for (int ty = bx.tyl; ty <= bx.tyh; ++ty)
+                for (int tx = bx.txl; tx <= bx.txh; ++tx)
+                    sum += slotv[i * a.nslot + (ty - bx.tyl) * a.spx + (tx - bx.txl)];
+            pv[i] = sj * sum;
+        }
+        mark(j, 4);
+        const double upj = stencil_at<TB>(V + (long long)j * ld, p, ny, nx, r, a.bc, tyl, txl, s_red);
+        mark(j, 5);
+        if (threadIdx.x == 0) pv[j] = sj * upj;
+        __syncthreads();
+        if (threadIdx.x < 64) forward_subst<TB>(Pl, k, pv, j + 1, h_l);
+        __syncthreads();
+        mark(j, 6);
+        for (int i = threadIdx.x; i <= j; i += NT) hs_l[i] = h_l[i] * sc_l[i];
+        if (tile == 0)
+            for (int i = threadIdx.x; i <= j; i += NT) a.H[(long long)j * kp1 + i] = h_l[i];
+        // ---- 4. the tile: u = A l_j = s_j * blur(v_j)
+        mark(j, 12);
+        blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert, wt,
+                      (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
+        mark(j, 7);
+        double acc[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
+        for (int e = threadIdx.x; e < TY * TX; e += NT) wt[e] *= sj;
+        __syncthreads();
+        auto skpart = [&](uint32_t stream, double scale, long long* part) {
+            if constexpr (SK == SK_SPARSE) {
+                if (tab2) {
+                    sketch_sparse_partial_tab(wt, tm, a.s, a.zeta, stream == 2u ? tab2 : tab1, scale,
+                                              (long long*)sk, part + (long long)tile * a.s);
+                    return;
+                }
+            }
+            sketch_partial<TB, SK>(a, wt, a.spm, tm, stream, scale, sk, part, tile);
+        };
+        skpart(2u, a.scz, a.zpart + par * GS);   // z_j
+        mark(j, 15);
+        if (j == 0) {   // c = S2 b = S2 v_0
+            for (int e = threadIdx.x; e < TY * TX; e += NT) {
+                const int yy = e / TX, xx = e - yy * TX;
+                wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
+            }
+            __syncthreads();
+            skpart(2u, scc, a.cpart);
+        }
+        if (a.lam > 0.0) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
+            for (int e = threadIdx.x; e < TY * TX; e += NT) {
+                const int yy = e / TX, xx = e - yy * TX;
+                wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
+            }
+            __syncthreads();
+            skpart(1u, scf_j, a.fpart + par * GS);
+        }
+        __syncthreads();
+        mark(j, 8);
+        // v_{j+1} = u - sum_i (h_i s_i) v_i
+        eliminate<TB, EPT>(acc, gm, V, ld, hs_l, j + 1);
+        mark(j, 9);
+        zero_pivots<EPT>(acc, vm, pm.bits);
+        tile_argmax<EPT>(acc, gm, vm, a.amv + par * G, a.ami + par * G, tile);
+        TB* dst = V + (long long)(j + 1) * ld;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const TB vv = (TB)acc[i];
+            if ((vm >> i) & 1u) dst[gm[i]] = vv;
+            const int e = threadIdx.x + i * NT;
+            if (e < TY * TX) wt[e] = ((vm >> i) & 1u) ? (double)vv : 0.0;
+        }
+        __syncthreads();
+        mark(j, 10);
+        // window sums of A v_{j+1} at the pivots p_0..p_j over this tile's pixels
+        {
+            const int nw = s_nw;
+            for (int q = 0; q < nw; ++q) {
+                const int i = wlist[q];
+                const int py = pivs[i] / nx, px = pivs[i] - (pivs[i] / nx) * nx;
+                double acc2 = 0.0;
+                for (int o = threadIdx.x; o < tw * tw; o += NT) {
+                    const int aa = o / tw, bb = o - aa * tw;
+                    const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
+                    if (y < tm.y0 || y >= tm.y0 + TY || x < tm.x0 || x >= tm.x0 + TX || y < 0 || x < 0) continue;
+                    acc2 = fma(tyl[aa] * txl[bb], wt[(y - tm.y0) * TX + (x - tm.x0)], acc2);
+                }
+                acc2 = wave_sum(acc2);
+                if ((threadIdx.x & 63) == 0) wred[q * NWAVE + (threadIdx.x >> 6)] = acc2;
+            }
+            __syncthreads();
+            double* wpc = a.wpart + (long long)par * kp1 * a.nslot;
+            for (int q = threadIdx.x; q < nw; q += NT) {
+                double sum = 0.0;
+                for (int w = 0; w < NWAVE; ++w) sum += wred[q * NWAVE + w];
+                const int i = wlist[q];
+                const WBox bx = wbox(pivs[i], ny, nx, r, TY, TX);
+                wpc[(long long)i * a.nslot + (tyi - bx.tyl) * a.spx + (txi - bx.txl)] = sum;
+            }
+        }
+        mark(j, 11);
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+    }
+}
+
+}  // namespace hk

@@ -1,0 +1,1130 @@
+// gfx950 kernels for the sketched inner-product-free Krylov methods.
+//
+// One persistent cooperative kernel runs the whole basis iteration of a solve
+// (Sec. 3.1: Hessenberg process with partial pivoting, eq. (Hessenberg_s);
+// generalized Hessenberg process, eq. (Hessenberg_r), Algorithm 1).  Each
+// workgroup owns one tile of the data space (and, for sLSLU, one tile of the
+// unknowns) for the whole solve, so the new basis vector it produces stays in
+// registers across the grid-wide argmax and is written to HBM exactly once.
+// Per step (square case) the phases are
+//   A: u = A l_j on the tile (FP64), S2-sketch partials of u, u at own pivots
+//   B: coefficients h = P^{-1} u(pivots) (forward substitution on the pivot
+//      block), v = u - L_j h streamed over the tile's basis rows, exact zeros
+//      at pivot rows, per-tile argmax |v|
+//   C: global argmax -> new pivot, l_{j+1} = v / v(pivot), S1-sketch partials
+// separated by grid barriers (bounded spin, abort flag: every wave exits).
+// No inner product is formed anywhere in the iteration.
+#pragma once
+#include "hk_internal.hpp"
+
+#include <climits>
+
+namespace hk {
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, multipliers 0xD2511F53
+// and 0xCD9E8D57, key schedule advanced by 0x9E3779B9 / 0xBB67AE85.
+// ------------------------------------------------------------------------
+struct Words { uint32_t w[4]; };
+
+__device__ __forceinline__ Words philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                          uint32_t key0, uint32_t key1)
+{
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        const uint32_t a_hi = __umulhi(0xD2511F53u, x0), a_lo = 0xD2511F53u * x0;
+        const uint32_t b_hi = __umulhi(0xCD9E8D57u, x2), b_lo = 0xCD9E8D57u * x2;
+        const uint32_t y0 = b_hi ^ x1 ^ key0;
+        const uint32_t y2 = a_hi ^ x3 ^ key1;
+        x0 = y0; x1 = b_lo; x2 = y2; x3 = a_lo;
+        key0 += 0x9E3779B9u;
+        key1 += 0xBB67AE85u;
+    }
+    Words r;
+    r.w[0] = x0; r.w[1] = x1; r.w[2] = x2; r.w[3] = x3;
+    return r;
+}
+
+// Four standard normals of rows 4*grp .. 4*grp+3, column `col` of the Gaussian
+// embedding: Box-Muller on the uniforms (2*(w>>9)+1) 2^-24 of one Philox
+// block (counter (col, grp, stream, 0)).  FP32 storage generates in FP32.
+template <typename TS>
+__device__ __forceinline__ void gauss4(uint32_t col, uint32_t grp, uint32_t stream, uint32_t k0,
+                                       uint32_t k1, double g[4]);
+
+template <>
+__device__ __forceinline__ void gauss4<double>(uint32_t col, uint32_t grp, uint32_t stream,
+                                               uint32_t k0, uint32_t k1, double g[4])
+{
+    Words w = philox10(col, grp, stream, 0u, k0, k1);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const double ua = (double)(2u * (w.w[2 * p] >> 9) + 1u) * 0x1p-24;
+        const double ub = (double)(2u * (w.w[2 * p + 1] >> 9) + 1u) * 0x1p-24;
+        const double rad = sqrt(-2.0 * log(ua));
+        double sn, cs;
+        sincospi(2.0 * ub, &sn, &cs);
+        g[2 * p] = rad * cs;
+        g[2 * p + 1] = rad * sn;
+    }
+}
+
+template <>
+__device__ __forceinline__ void gauss4<float>(uint32_t col, uint32_t grp, uint32_t stream,
+                                              uint32_t k0, uint32_t k1, double g[4])
+{
+    Words w = philox10(col, grp, stream, 0u, k0, k1);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float ua = (float)(2u * (w.w[2 * p] >> 9) + 1u) * 0x1p-24f;
+        const float ub = (float)(2u * (w.w[2 * p + 1] >> 9) + 1u) * 0x1p-24f;
+        const float rad = sqrtf(-2.0f * logf(ua));
+        float sn, cs;
+        sincospif(2.0f * ub, &sn, &cs);
+        g[2 * p] = (double)(rad * cs);
+        g[2 * p + 1] = (double)(rad * sn);
+    }
+}
+
+// ------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// (|v|, index) ordering: larger magnitude wins, ties go to the smaller index.
+__device__ __forceinline__ bool am_better(double a1, int i1, double a2, int i2)
+{
+    return a1 > a2 || (a1 == a2 && i1 < i2);
+}
+
+__device__ __forceinline__ void wave_argmax(double& best, int& idx, double& val)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(idx, o);
+        const double ov = __shfl_xor(val, o);
+        if (am_better(ob, oi, best, idx)) { best = ob; idx = oi; val = ov; }
+    }
+}
+
+__device__ __forceinline__ int bc_map(int i, int N, int bc)
+{
+    if (i >= 0 && i < N) return i;
+    if (bc == 0) return -1;
+    if (i < 0) i = -i - 1;
+    if (i >= N) i = 2 * N - i - 1;
+    return (i >= 0 && i < N) ? i : -1;
+}
+
+// ------------------------------------------------------------------------
+// tiles
+// ------------------------------------------------------------------------
+struct Tile {
+    int start;   // 1-D: first global index
+    int E;       // elements (2-D: TY*TX slots, some may lie outside the image)
+    int y0, x0;  // 2-D origin
+};
+
+__device__ __forceinline__ int range_start(int t, int len, int ntile)
+{
+    return (int)(((long long)t * len) / ntile);
+}
+
+__device__ __forceinline__ Tile tile_info(const Space& sp, int t)
+{
+    Tile ti;
+    if (sp.kind == 0) {
+        ti.y0 = (t / sp.ntx) * sp.TY;
+        ti.x0 = (t % sp.ntx) * sp.TX;
+        ti.E = sp.TY * sp.TX;
+        ti.start = 0;
+    } else {
+        ti.start = range_start(t, sp.len, sp.ntile);
+        ti.E = range_start(t + 1, sp.len, sp.ntile) - ti.start;
+        ti.y0 = ti.x0 = 0;
+    }
+    return ti;
+}
+
+__device__ __forceinline__ bool elem_global(const Space& sp, const Tile& ti, int e, int& gi)
+{
+    if (e >= ti.E) return false;
+    if (sp.kind == 0) {
+        const int y = ti.y0 + e / sp.TX, x = ti.x0 + e % sp.TX;
+        gi = y * sp.nx + x;
+        return y < sp.ny && x < sp.nx;
+    }
+    gi = ti.start + e;
+    return true;
+}
+
+// tile and local element that own global index gi
+__device__ __forceinline__ void owner_of(const Space& sp, int gi, int& t, int& e)
+{
+    if (sp.kind == 0) {
+        const int y = gi / sp.nx, x = gi % sp.nx;
+        t = (y / sp.TY) * sp.ntx + x / sp.TX;
+        e = (y % sp.TY) * sp.TX + (x % sp.TX);
+    } else {
+        int c = (int)(((long long)gi * sp.ntile) / sp.len);
+        while (c + 1 < sp.ntile && range_start(c + 1, sp.len, sp.ntile) <= gi) ++c;
+        while (c > 0 && range_start(c, sp.len, sp.ntile) > gi) --c;
+        t = c;
+        e = gi - range_start(c, sp.len, sp.ntile);
+    }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of tiles so stencil halos are shared inside one L2.
+__device__ __forceinline__ int tile_of_block(int G, int xcd_map)
+{
+    const int b = blockIdx.x;
+    if (!xcd_map) return b;
+    return (b % 8) * (G / 8) + b / 8;
+}
+
+// ------------------------------------------------------------------------
+// Grid barrier, hierarchical over the XCDs (each has its own L2).
+//  - every wave drains its stores (s_waitcnt 0): they are in its XCD's L2;
+//  - one thread per workgroup counts the arrival on its XCD's counter;
+//  - the last arriver of an XCD writes that L2 back (agent release), counts
+//    the XCD on the global counter, spins (bounded) until all XCDs arrived,
+//    acquires, and publishes the epoch on its XCD's release flag;
+//  - the other workgroups of the XCD spin on that flag and acquire (L1/L2
+//    invalidate), so reads after the barrier see every workgroup's writes.
+// One atomic per workgroup goes to its XCD line and one per XCD to the
+// global line.  Every wait is bounded: on timeout the abort flag is raised
+// and every waiter returns false.
+// ------------------------------------------------------------------------
+struct BarState {
+    unsigned xcd, pop, nxcd, gbase, epoch;
+};
+
+__device__ __forceinline__ unsigned hw_xcc_id()
+{
+    // hardware register XCC_ID (id 20), bits [3:0]: the XCD this wave runs on
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((16 - 1) << 11)) & 0xfu;
+}
+
+__device__ __forceinline__ bool spin_until(unsigned* p, unsigned target, Ctl* ctl,
+                                           unsigned long long timeout)
+{
+    const unsigned long long t0 = wall_clock64();
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() - t0 > timeout) {
+            __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
+// Start-up: count the workgroups of each XCD (one flat barrier).
+__device__ bool hbar_init(Ctl* ctl, BarState& bs, unsigned G, unsigned long long timeout)
+{
+    __shared__ int s_ok;
+    __shared__ unsigned s_xcd, s_pop, s_nx;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned x = hw_xcc_id();
+        __hip_atomic_fetch_add(&ctl->pop[x].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&ctl->gcnt.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ok = spin_until(&ctl->gcnt.v, G, ctl, timeout);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        unsigned nx = 0;
+        for (int i = 0; i < 16; ++i)
+            nx += __hip_atomic_load(&ctl->pop[i].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+        s_xcd = x;
+        s_pop = __hip_atomic_load(&ctl->pop[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_nx = nx;
+        s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    bs.xcd = s_xcd;
+    bs.pop = s_pop;
+    bs.nxcd = s_nx;
+    bs.gbase = G;
+    bs.epoch = 0;
+    return s_ok != 0;
+}
+
+__device__ bool hbar_sync(Ctl* ctl, BarState& bs, unsigned long long timeout,
+                          unsigned long long* trace = nullptr, int trace_cap = 0)
+{
+    __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const unsigned ep = ++bs.epoch;
+    if (threadIdx.x == 0) {
+        const bool tr = trace && blockIdx.x == 0 && (int)(2 * ep) <= trace_cap;
+        if (tr) trace[2 * (ep - 1)] = wall_clock64();
+        bool ok;
+        const unsigned old = __hip_atomic_fetch_add(&ctl->xcnt[bs.xcd].v, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old == ep * bs.pop - 1) {           // last workgroup of this XCD
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(&ctl->gcnt.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = spin_until(&ctl->gcnt.v, bs.gbase + ep * bs.nxcd, ctl, timeout);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(&ctl->xflag[bs.xcd].v, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = spin_until(&ctl->xflag[bs.xcd].v, ep, ctl, timeout);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        if (tr) trace[2 * (ep - 1) + 1] = wall_clock64();
+        if (blockIdx.x == 0) ctl->nbar = (int)ep;
+        s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ------------------------------------------------------------------------
+// operator products on one tile -> wt[e] (FP64, LDS)
+// ------------------------------------------------------------------------
+// Separable blur: stage the tile plus an r-pixel halo (boundary condition
+// applied while staging), vertical pass into FP64, horizontal pass.
+template <typename TS>
+__device__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int bc, const Tile& ti,
+                          int TY, int TX, const double* tyl, const double* txl, TS* stage,
+                          double* vert, double* wt, unsigned long long* tmk = nullptr)
+{
+    const int SW = TX + 2 * r, SH = TY + 2 * r;
+    constexpr int SB = 8;                        // loads in flight per thread
+    for (int q0 = 0; q0 < SH * SW; q0 += SB * NT) {
+        TS v[SB];
+        bool in[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int q = q0 + u * NT + (int)threadIdx.x;
+            const int yy = q / SW, xx = q - yy * SW;
+            const int y = bc_map(ti.y0 - r + yy, ny, bc);
+            const int xg = bc_map(ti.x0 - r + xx, nx, bc);
+            in[u] = (q < SH * SW) && y >= 0 && xg >= 0;
+            v[u] = x[in[u] ? y * nx + xg : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int q = q0 + u * NT + (int)threadIdx.x;
+            if (q < SH * SW) stage[q] = in[u] ? v[u] : TS(0);
+        }
+    }
+    __syncthreads();
+    if (tmk && threadIdx.x == 0) tmk[0] = wall_clock64();
+    const int taps = 2 * r + 1;
+    // vertical pass: each thread computes 4 consecutive rows of one column
+    // from a sliding window of 4 staged values (one LDS read, 4 independent
+    // FMAs per tap)
+    for (int it = threadIdx.x; it < (TY / 4) * SW; it += NT) {
+        const int g = it / SW, xx = it - g * SW;
+        const TS* col = stage + (4 * g) * SW + xx;
+        double s0 = (double)col[0], s1 = (double)col[SW], s2 = (double)col[2 * SW];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int b = 0; b < taps; ++b) {
+            const double s3 = (double)col[(b + 3) * SW];
+            const double w = tyl[b];
+            a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, s3, a3);
+            s0 = s1; s1 = s2; s2 = s3;
+        }
+        double* vo = vert + (4 * g) * SW + xx;
+        vo[0] = a0; vo[SW] = a1; vo[2 * SW] = a2; vo[3 * SW] = a3;
+    }
+    __syncthreads();
+    if (tmk && threadIdx.x == 0) tmk[1] = wall_clock64();
+    // horizontal pass: 2 consecutive outputs of one row per thread
+    for (int it = threadIdx.x; it < TY * (TX / 2); it += NT) {
+        const int yy = it / (TX / 2), x2 = it - yy * (TX / 2);
+        const double* row = vert + yy * SW + 2 * x2;
+        double s0 = row[0];
+        double a0 = 0.0, a1 = 0.0;
+        for (int b = 0; b < taps; ++b) {
+            const double s1 = row[b + 1];
+            const double w = txl[b];
+            a0 = fma(w, s0, a0); a1 = fma(w, s1, a1);
+            s0 = s1;
+        }
+        wt[yy * TX + 2 * x2] = a0;
+        wt[yy * TX + 2 * x2 + 1] = a1;
+    }
+    __syncthreads();
+}
+
+// CSR rows [start, start+E): groups of `lpr` lanes per row, FP64 accumulation.
+template <typename TV, typename TX>
+__device__ void csr_tile(const int64_t* __restrict__ rp, const int* __restrict__ ci,
+                         const TV* __restrict__ cv, const TX* __restrict__ x, const Tile& ti,
+                         int lpr, double* wt)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rpw = 64 / lpr;
+    const int sub = lane / lpr, sl = lane - sub * lpr;
+    for (int base = wave * rpw; base < ti.E; base += NWAVE * rpw) {
+        const int e = base + sub;
+        double acc = 0.0;
+        if (e < ti.E) {
+            const long long p0 = rp[ti.start + e], p1 = rp[ti.start + e + 1];
+            long long p = p0 + sl;
+            // batches of 4 entries per lane: indices and values, then the
+            // gathers, then the FMAs (in entry order)
+            for (; p + 3 * lpr < p1; p += 4 * lpr) {
+                int c4[4];
+                TV v4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) { c4[u] = ci[p + u * lpr]; v4[u] = cv[p + u * lpr]; }
+                TX x4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x4[u] = x[c4[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc = fma((double)v4[u], (double)x4[u], acc);
+            }
+            for (; p < p1; p += lpr) acc = fma((double)cv[p], (double)x[ci[p]], acc);
+        }
+        for (int o = lpr >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (sl == 0 && e < ti.E) wt[e] = acc;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------
+// sketch partial sums of a tile vector vals[e] (FP64, LDS)
+// ------------------------------------------------------------------------
+// Sparse sign (zeta nonzeros +-1/sqrt(zeta) per column, one per row block
+// [b s/zeta, (b+1) s/zeta), block b from word b%4 of Philox (col, b/4,
+// stream, 1)).  Terms are accumulated as int64 fixed point: exact, so the
+// sum does not depend on the order of the LDS atomics.  out[r] holds sum of
+// sign * round(v * scale) over the tile.
+__device__ void sketch_sparse_partial(const double* vals, const Space& sp, const Tile& ti, int s,
+                                      int zeta, uint32_t stream, uint32_t k0, uint32_t k1,
+                                      double scale, long long* acc, long long* out)
+{
+    for (int r = threadIdx.x; r < s; r += NT) acc[r] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < ti.E; e += NT) {
+        int gi;
+        if (!elem_global(sp, ti, e, gi)) continue;
+        const long long q = __double2ll_rn(vals[e] * scale);
+        if (q == 0) continue;
+        for (int b4 = 0; b4 < zeta; b4 += 4) {
+            const Words w = philox10((uint32_t)gi, (uint32_t)(b4 >> 2), stream, 1u, k0, k1);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int b = b4 + qq;
+                if (b >= zeta) break;
+                // block boundaries floor(b s / zeta): b s < 2^31 for s < 2^15
+                const int st = (int)((unsigned)(b * s) / (unsigned)zeta);
+                const int en = (int)((unsigned)((b + 1) * s) / (unsigned)zeta);
+                const uint32_t word = w.w[qq];
+                const int row = st + (int)(((unsigned long long)(word >> 1) * (unsigned)(en - st)) >> 31);
+                atomicAdd((unsigned long long*)&acc[row], (unsigned long long)((word & 1u) ? -q : q));
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < s; r += NT) out[r] = acc[r];
+}
+
+// Gaussian: out[r] = sum_e g(r, col(e)) * vals[e] (unscaled normals).  Each
+// thread owns one row group (4 rows) and a strided subset of the elements,
+// summed in element order; the nsub subsets of a row group sit in adjacent
+// lanes and are added by a fixed xor-shuffle tree: deterministic.
+template <typename TS>
+__device__ void sketch_gauss_partial(const double* vals, const Space& sp, const Tile& ti, int s,
+                                     uint32_t stream, uint32_t k0, uint32_t k1, double* red,
+                                     double* out)
+{
+    const int NG = (s + 3) >> 2;
+    int nsub = 1;
+    while (nsub * 2 <= 64 && nsub * 2 * NG <= NT) nsub *= 2;
+    for (int base = 0; base < NG * nsub; base += NT) {
+        const int t = base + threadIdx.x;
+        const int rg = t / nsub, es = t - rg * nsub;
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        if (rg < NG) {
+            for (int e = es; e < ti.E; e += nsub) {
+                int gi;
+                if (!elem_global(sp, ti, e, gi)) continue;
+                const double v = vals[e];
+                double g[4];
+                gauss4<TS>((uint32_t)gi, (uint32_t)rg, stream, k0, k1, g);
+                a0 = fma(g[0], v, a0); a1 = fma(g[1], v, a1); a2 = fma(g[2], v, a2); a3 = fma(g[3], v, a3);
+            }
+        }
+        for (int o = nsub >> 1; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o); a1 += __shfl_xor(a1, o);
+            a2 += __shfl_xor(a2, o); a3 += __shfl_xor(a3, o);
+        }
+        if (rg < NG && es == 0) {
+            red[4 * rg] = a0; red[4 * rg + 1] = a1; red[4 * rg + 2] = a2; red[4 * rg + 3] = a3;
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < s; r += NT) out[r] = red[r];
+    __syncthreads();
+}
+
+// Sparse sign from a table built once per solve: tab[e * zeta + b] holds
+// (row << 1) | negative for block b of element e's column.
+__device__ void sketch_sparse_partial_tab(const double* vals, const Tile& ti, int s, int zeta,
+                                          const unsigned short* tab, double scale, long long* acc,
+                                          long long* out)
+{
+    for (int r = threadIdx.x; r < s; r += NT) acc[r] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < ti.E; e += NT) {
+        const long long q = __double2ll_rn(vals[e] * scale);
+        if (q == 0) continue;
+        const unsigned short* te = tab + e * zeta;
+        for (int b = 0; b < zeta; ++b) {
+            const unsigned ent = te[b];
+            atomicAdd((unsigned long long*)&acc[ent >> 1], (unsigned long long)((ent & 1u) ? -q : q));
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < s; r += NT) out[r] = acc[r];
+}
+
+// Build the table for the tile's elements (invalid elements get zero values
+// in vals, so their entries are never used).
+__device__ void sketch_sparse_table(const Space& sp, const Tile& ti, int s, int zeta, uint32_t stream,
+                                    uint32_t k0, uint32_t k1, unsigned short* tab)
+{
+    for (int e = threadIdx.x; e < ti.E; e += NT) {
+        int gi;
+        if (!elem_global(sp, ti, e, gi)) gi = 0;
+        for (int b4 = 0; b4 < zeta; b4 += 4) {
+            const Words w = philox10((uint32_t)gi, (uint32_t)(b4 >> 2), stream, 1u, k0, k1);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int b = b4 + qq;
+                if (b >= zeta) break;
+                const int st = (int)((unsigned)(b * s) / (unsigned)zeta);
+                const int en = (int)((unsigned)((b + 1) * s) / (unsigned)zeta);
+                const uint32_t word = w.w[qq];
+                const int row = st + (int)(((unsigned long long)(word >> 1) * (unsigned)(en - st)) >> 31);
+                tab[e * zeta + b] = (unsigned short)((row << 1) | (int)(word & 1u));
+            }
+        }
+    }
+}
+
+template <typename TS, int SK>
+__device__ __forceinline__ void sketch_partial(const KArgs& a, const double* vals, const Space& sp,
+                                               const Tile& ti, uint32_t stream, double scale,
+                                               unsigned char* sk, long long* part, int tile)
+{
+    if constexpr (SK == SK_SPARSE) {
+        sketch_sparse_partial(vals, sp, ti, a.s, a.zeta, stream, a.seed_lo, a.seed_hi, scale,
+                              (long long*)sk, part + (long long)tile * a.s);
+    } else {
+        sketch_gauss_partial<TS>(vals, sp, ti, a.s, stream, a.seed_lo, a.seed_hi, (double*)sk,
+                                 (double*)(part + (long long)tile * a.s));
+    }
+}
+
+// Reduce the G partials of this workgroup's slice of sketch rows into out[]
+// (one wave per row, fixed order).
+template <int SK>
+__device__ void reduce_partials(const KArgs& a, const long long* part, double inv, int tile, double* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = (int)(((long long)tile * a.s) / a.G), r1 = (int)(((long long)(tile + 1) * a.s) / a.G);
+    for (int r = r0 + wave; r < r1; r += NWAVE) {
+        if constexpr (SK == SK_SPARSE) {
+            long long v[MAXG / 64];
+#pragma unroll
+            for (int u = 0; u < MAXG / 64; ++u) {
+                const int q = lane + 64 * u;
+                v[u] = part[(long long)(q < a.G ? q : 0) * a.s + r];
+            }
+            long long acc = 0;
+#pragma unroll
+            for (int u = 0; u < MAXG / 64; ++u)
+                if (lane + 64 * u < a.G) acc += v[u];
+            acc = wave_sum_ll(acc);
+            if (lane == 0) out[r] = (double)acc * inv;
+        } else {
+            const double* pd = (const double*)part;
+            double v[MAXG / 64];
+#pragma unroll
+            for (int u = 0; u < MAXG / 64; ++u) {
+                const int q = lane + 64 * u;
+                v[u] = pd[(long long)(q < a.G ? q : 0) * a.s + r];
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < MAXG / 64; ++u)
+                if (lane + 64 * u < a.G) acc += v[u];
+            acc = wave_sum(acc);
+            if (lane == 0) out[r] = acc * inv;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// coefficients: h = P^{-1} pv with P the unit lower triangular pivot block
+// (P(i, c) = basis_c(pivot_i)), held in LDS as a column-packed strict lower
+// triangle of a (k+1) x (k+1) block.  Column-oriented forward substitution by
+// wave 0: h_c is final when column c is reached; the next column is read from
+// LDS while the current one is applied.
+// ------------------------------------------------------------------------
+template <typename TS, int NQ>
+__device__ __forceinline__ void forward_subst_nq(const TS* __restrict__ Pl, int k, const double* __restrict__ pv,
+                                                 int nh, double* h)
+{
+    const int lane = threadIdx.x & 63;
+    const int plast = (int)packed_size(k) - 1;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        v[q] = (i < nh) ? pv[i] : 0.0;
+    }
+    // The value loaded for column c is zero wherever row i <= c or i >= nh,
+    // so the update v -= P(:, c) h_c needs no mask (fma(-0, h, v) == v) and
+    // the step's critical path is readlane -> fma.
+    double nxt[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        const TS t = Pl[min(max(i - 1, 0), plast)];       // column 0: P(i, 0)
+        nxt[q] = (i > 0 && i < nh) ? (double)t : 0.0;
+    }
+    for (int c = 0; c + 1 < nh; ++c) {
+        double colv[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) colv[q] = nxt[q];
+        const int base = packed_col(c + 1, k) - (c + 2);    // base + i = position of P(i, c+1)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int i = lane + 64 * q;
+            const TS t = Pl[min(max(base + i, 0), plast)];
+            nxt[q] = (i > c + 1 && i < nh) ? (double)t : 0.0;
+        }
+        double src = v[0];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+            if ((c >> 6) == q) src = v[q];
+        const double hc = readlane_d(src, c & 63);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = fma(-colv[q], hc, v[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        if (i < nh) h[i] = v[q];
+    }
+}
+
+template <typename TS>
+__device__ __forceinline__ void forward_subst(const TS* __restrict__ Pl, int k, const double* __restrict__ pv,
+                                              int nh, double* h)
+{
+    const int nq = (nh + 63) >> 6;
+    if (nq <= 1) forward_subst_nq<TS, 1>(Pl, k, pv, nh, h);
+    else if (nq == 2) forward_subst_nq<TS, 2>(Pl, k, pv, nh, h);
+    else if (nq == 3) forward_subst_nq<TS, 3>(Pl, k, pv, nh, h);
+    else forward_subst_nq<TS, 4>(Pl, k, pv, nh, h);
+}
+
+// Copy row i (entries c < i) of the row-major global pivot block into the
+// packed LDS copy.
+template <typename TS>
+__device__ __forceinline__ void lds_append_row(TS* Pl, int k, const TS* __restrict__ P, int kp1, int i)
+{
+    for (int c = threadIdx.x; c < i; c += NT) Pl[packed_col(c, k) + (i - c - 1)] = P[(long long)i * kp1 + c];
+}
+
+// Bulk-load rows 1..nh-1 of the global pivot block into the packed LDS layout.
+template <typename TS>
+__device__ void lds_load_block(TS* Pl, int k, const TS* __restrict__ P, int kp1, int nh)
+{
+    const int tot = nh * (nh - 1) / 2;
+    for (int e = threadIdx.x; e < tot; e += NT) {
+        int i = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)e)) * 0.5f);
+        while (i * (i - 1) / 2 > e) --i;
+        while ((i + 1) * i / 2 <= e) ++i;
+        const int c = e - i * (i - 1) / 2;
+        Pl[packed_col(c, k) + (i - c - 1)] = P[(long long)i * kp1 + c];
+    }
+}
+
+// v -= sum_c h[c] * B_c over the thread's elements, columns in increasing
+// order.  gi holds a valid index for every slot (masked slots point at a real
+// element and are ignored by the caller), so all U * EPT loads of a batch
+// issue back to back without branches.
+template <typename TS, int EPT>
+__device__ __forceinline__ void eliminate(double (&acc)[EPT], const int (&gi)[EPT],
+                                          const TS* __restrict__ B, long long ld, const double* h,
+                                          int ncols)
+{
+    constexpr int U = (EPT == 1) ? 32 : ((EPT == 2) ? 8 : 4);
+    // unsigned 32-bit byte offsets: loads use a uniform column base + offset
+    unsigned off[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) off[i] = (unsigned)gi[i] * (unsigned)sizeof(TS);
+    const char* base = (const char*)B;
+    const unsigned long long ldb = (unsigned long long)ld * sizeof(TS);
+    int c = 0;
+    for (; c + U <= ncols; c += U) {
+        TS xv[U][EPT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const char* col = base + (unsigned long long)(c + u) * ldb;
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) xv[u][i] = *(const TS*)(col + off[i]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double hu = h[c + u];
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) acc[i] = fma(-hu, (double)xv[u][i], acc[i]);
+        }
+    }
+    for (; c < ncols; ++c) {
+        const char* col = base + (unsigned long long)c * ldb;
+        const double hu = h[c];
+        TS xv[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) xv[i] = *(const TS*)(col + off[i]);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) acc[i] = fma(-hu, (double)xv[i], acc[i]);
+    }
+}
+
+// Per-tile argmax |v| (ties: smallest index) -> amv[slot], ami[slot];
+// a non-finite value marks the slot with index -2.
+template <int EPT>
+__device__ void tile_argmax(const double (&acc)[EPT], const int (&gi)[EPT], unsigned vmask,
+                            double* amv, int* ami, int slot)
+{
+    __shared__ double s_b[NWAVE], s_v[NWAVE];
+    __shared__ int s_i[NWAVE], s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    double best = -1.0, val = 0.0;
+    int idx = INT_MAX;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        if (!((vmask >> i) & 1u)) continue;
+        const double v = acc[i];
+        if (!isfinite(v)) bad = true;
+        const double av = fabs(v);
+        if (am_better(av, gi[i], best, idx)) { best = av; idx = gi[i]; val = v; }
+    }
+    wave_argmax(best, idx, val);
+    __syncthreads();
+    if (bad) s_bad = 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_b[wave] = best; s_i[wave] = idx; s_v[wave] = val; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w)
+            if (am_better(s_b[w], s_i[w], best, idx)) { best = s_b[w]; idx = s_i[w]; val = s_v[w]; }
+        amv[slot] = val;
+        ami[slot] = s_bad ? -2 : idx;
+    }
+}
+
+// Reduce the G tile partials at amv[off..off+G) (every workgroup does the
+// same reduction, so all agree).  Returns the signed value and the index;
+// idx = -2 flags non-finite data.
+__device__ void global_argmax(const double* amv, const int* ami, int off, int G, double& val, int& idx)
+{
+    __shared__ double s_val;
+    __shared__ int s_idx;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double best = -1.0, v = 0.0;
+        int bi = INT_MAX;
+        int bad = 0;
+        int iv[MAXG / 64];
+        double vv[MAXG / 64];
+#pragma unroll
+        for (int u = 0; u < MAXG / 64; ++u) {
+            const int q = lane + 64 * u;
+            const int qq = off + (q < G ? q : 0);
+            iv[u] = ami[qq];
+            vv[u] = amv[qq];
+        }
+#pragma unroll
+        for (int u = 0; u < MAXG / 64; ++u) {
+            if (lane + 64 * u >= G) continue;
+            if (iv[u] == -2) bad = 1;
+            if (am_better(fabs(vv[u]), iv[u], best, bi)) { best = fabs(vv[u]); bi = iv[u]; v = vv[u]; }
+        }
+        wave_argmax(best, bi, v);
+        for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o);
+        if (lane == 0) { s_val = v; s_idx = bad ? -2 : bi; }
+    }
+    __syncthreads();
+    val = s_val;
+    idx = s_idx;
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------
+// per-space state kept in LDS across the whole solve
+// ------------------------------------------------------------------------
+struct PivState {
+    int* list_e;     // local element of each pivot in this tile
+    int* list_c;     // basis column of that pivot
+    unsigned* bits;  // bitmap of pivot elements of this tile
+    int* count;      // number of pivots in this tile
+};
+
+template <int EPT>
+__device__ __forceinline__ void zero_pivots(double (&acc)[EPT], unsigned vmask, const unsigned* bits)
+{
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (((vmask >> i) & 1u) && ((bits[e >> 5] >> (e & 31)) & 1u)) acc[i] = 0.0;
+    }
+}
+
+// New pivot p found in column col: if this tile owns it, record it and
+// write row col of the global, row-major pivot block (P(col, c) = B_c(p),
+// P(col, col) = 1).
+template <typename TS>
+__device__ void add_pivot(const Space& sp, int tile, int p, int col, PivState& ps, TS* P, int kp1,
+                          const TS* B, long long ld)
+{
+    int ot, oe;
+    owner_of(sp, p, ot, oe);
+    if (ot != tile) return;
+    for (int c = threadIdx.x; c < col; c += NT) P[(long long)col * kp1 + c] = B[(long long)c * ld + p];
+    if (threadIdx.x == 0) {
+        P[(long long)col * kp1 + col] = TS(1);
+        const int n = *ps.count;
+        ps.list_e[n] = oe;
+        ps.list_c[n] = col;
+        *ps.count = n + 1;
+        ps.bits[oe >> 5] |= 1u << (oe & 31);
+    }
+}
+
+// ------------------------------------------------------------------------
+// the persistent basis-iteration kernel
+// ------------------------------------------------------------------------
+// TB: storage type of the bases; TO: storage type of the operator values,
+// of b and of x.
+template <typename TB, typename TO, int OP, int SK, int EPT>
+__global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_cnt_m, s_cnt_n;
+    double* h_l = (double*)(smem + a.lds_h);
+    double* wt = (double*)(smem + a.lds_w);
+    unsigned char* sk = smem + a.lds_sk;
+    TB* stage = (TB*)(smem + a.lds_stage);
+    double* vert = (double*)(smem + a.lds_vert);
+    double* taps = (double*)(smem + a.lds_taps);
+    TB* PlD = (TB*)(smem + a.lds_pD);     // packed pivot block of the data-space basis
+    TB* PlL = (TB*)(smem + a.lds_pL);     // ... of L (sLSLU; same buffer in bulk mode)
+
+    const int G = a.G;
+    const int tile = tile_of_block(G, a.xcd_map);
+    const int kp1 = a.k + 1;
+    const bool rect = a.rect != 0;
+    Ctl* ctl = a.ctl;
+    BarState bs;
+
+    PivState pm{(int*)(smem + a.lds_pl_m), (int*)(smem + a.lds_pc_m), (unsigned*)(smem + a.lds_bm_m), &s_cnt_m};
+    PivState pn{(int*)(smem + a.lds_pl_n), (int*)(smem + a.lds_pc_n), (unsigned*)(smem + a.lds_bm_n), &s_cnt_n};
+    if (!rect) pn = pm;
+
+    const Tile tm = tile_info(a.spm, tile);
+    const Tile tn = rect ? tile_info(a.spn, tile) : tm;
+
+    // LDS init
+    for (int q = threadIdx.x; q < (NT * EPT + 31) / 32; q += NT) {
+        pm.bits[q] = 0u;
+        if (rect) pn.bits[q] = 0u;
+    }
+    if (threadIdx.x == 0) { s_cnt_m = 0; s_cnt_n = 0; }
+    if constexpr (OP == OP_BLUR) {
+        for (int q = threadIdx.x; q < 2 * a.r + 1; q += NT) {
+            taps[q] = a.taps_y[q];
+            taps[2 * a.r + 1 + q] = a.taps_x[q];
+        }
+    }
+    __syncthreads();
+
+    // element ownership of this thread in the m-tile (and n-tile)
+    int gm[EPT], gn[EPT];
+    unsigned vm = 0u, vn = 0u;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        int g = 0;
+        if (elem_global(a.spm, tm, e, g)) vm |= 1u << i; else g = 0;
+        gm[i] = g;
+        if (rect) {
+            g = 0;
+            if (elem_global(a.spn, tn, e, g)) vn |= 1u << i; else g = 0;
+            gn[i] = g;
+        } else {
+            gn[i] = gm[i];
+        }
+    }
+    if (!rect) vn = vm;
+
+    const TO* bvec = (const TO*)a.b;
+    TB* Lb = (TB*)a.L;
+    TB* Db = rect ? (TB*)a.D : Lb;   // basis of the data space
+    TB* PD = rect ? (TB*)a.PD : (TB*)a.PL;
+    TB* PL = (TB*)a.PL;
+    double* pvD = rect ? a.pvD : a.pvL;
+    double* pvL = a.pvL;
+    const long long ldd = rect ? a.ldd : a.ldl;
+    const double inv_sk = (SK == SK_SPARSE) ? 1.0 / sqrt((double)a.zeta) : 1.0 / sqrt((double)a.s);
+
+    auto op_forward = [&](const TB* xin) {   // wt = A xin on the m-tile
+        if constexpr (OP == OP_BLUR) {
+            blur_tile<TB>(xin, a.ny, a.nx, a.r, a.bc, tm, a.spm.TY, a.spm.TX, taps,
+                          taps + 2 * a.r + 1, stage, vert, wt);
+        } else {
+            csr_tile<TO, TB>(a.rp, a.ci, (const TO*)a.cv, xin, tm, a.lpr, wt);
+        }
+    };
+    auto op_adjoint = [&](const TB* xin) {   // wt = A^T xin on the n-tile
+        if constexpr (OP == OP_CSR) csr_tile<TO, TB>(a.rpt, a.cit, (const TO*)a.cvt, xin, tn, a.lprt, wt);
+    };
+    auto finish = [&](int k_done, int status, int nt, int ng) {
+        if (tile == 0 && threadIdx.x == 0) {
+            ctl->k_done = k_done;
+            ctl->nt = nt;
+            ctl->ng = ng;
+            if (ctl->status == 0) ctl->status = status;
+        }
+    };
+    auto fail = [&](int status) {
+        if (tile == 0 && threadIdx.x == 0) ctl->status = status;
+    };
+
+    double acc[EPT], accn[EPT];
+
+    if (!hbar_init(ctl, bs, (unsigned)G, a.timeout_ticks)) { fail(-3); return; }
+
+    // ---------------- setup: first pivot(s) and first basis vectors --------
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const double v = (double)bvec[gm[i]];
+        acc[i] = ((vm >> i) & 1u) ? v : 0.0;
+    }
+    tile_argmax<EPT>(acc, gm, vm, a.amv, a.ami, tile);
+    if (rect) {
+        if constexpr (OP == OP_CSR)                        // v0 = A^T b
+            csr_tile<TO, TO>(a.rpt, a.cit, (const TO*)a.cvt, bvec, tn, a.lprt, wt);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) accn[i] = ((vn >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
+        tile_argmax<EPT>(accn, gn, vn, a.amv, a.ami, G + tile);
+    }
+    if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+    double beta;
+    int p1;
+    global_argmax(a.amv, a.ami, 0, G, beta, p1);
+    double alpha = 0.0;
+    int g1 = 0;
+    if (rect) global_argmax(a.amv, a.ami, G, G, alpha, g1);
+    if (p1 == -2 || (rect && g1 == -2)) { fail(-4); return; }
+    if (beta == 0.0 || (rect && alpha == 0.0)) {
+        if (tile == 0 && threadIdx.x == 0 && beta != 0.0) a.tp[0] = p1;
+        finish(0, 1, beta != 0.0 ? 1 : 0, 0);
+        return;
+    }
+
+    // c partial = S2 b (scale from max|b| = |beta|)
+    const double scc = fx_scale((double)a.m * fabs(beta) * 1.000001);
+    for (int e = threadIdx.x; e < tm.E; e += NT) {
+        int gi;
+        wt[e] = elem_global(a.spm, tm, e, gi) ? (double)bvec[gi] : 0.0;
+    }
+    __syncthreads();
+    sketch_partial<TB, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
+    __syncthreads();
+
+    // d1 = b / beta (sLSLU) or l1 = b / beta (sCMRH)
+#pragma unroll
+    for (int i = 0; i < EPT; ++i)
+        if ((vm >> i) & 1u) Db[gm[i]] = (TB)(acc[i] / beta);
+    if (rect) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if ((vn >> i) & 1u) Lb[gn[i]] = (TB)(accn[i] / alpha);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    add_pivot<TB>(a.spm, tile, p1, 0, pm, PD, kp1, Db, ldd);
+    if (rect) add_pivot<TB>(a.spn, tile, g1, 0, pn, PL, kp1, Lb, a.ldl);
+    if (tile == 0 && threadIdx.x == 0) {
+        a.tp[0] = p1;
+        if (rect) { a.gp[0] = g1; a.W[0] = alpha / beta; }
+    }
+    if (a.lam > 0.0) {   // f_1 = S1 l_1
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (e < tn.E) wt[e] = ((vn >> i) & 1u) ? (double)(TB)(rect ? accn[i] / alpha : acc[i] / beta) : 0.0;
+        }
+        __syncthreads();
+        sketch_partial<TB, SK>(a, wt, a.spn, tn, 1u, a.scf, sk, a.fpart, tile);
+    }
+    if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+    const double inv_c = (SK == SK_SPARSE) ? inv_sk / scc : inv_sk;
+    const double inv_z = (SK == SK_SPARSE) ? inv_sk / a.scz : inv_sk;
+    const double inv_f = (SK == SK_SPARSE) ? inv_sk / a.scf : inv_sk;
+
+    // ---------------- basis iteration --------------------------------------
+    const TB* PDc = rect ? (const TB*)a.PD : (const TB*)a.PL;
+    for (int j = 0; j < a.k; ++j) {
+        const int nh = j + 1;
+        // ---- phase A: u = A l_j on the m-tile
+        if (a.pmode == 0 && j > 0) {        // rows j of the pivot blocks, written last step
+            lds_append_row<TB>(PlD, a.k, PDc, kp1, j);
+            if (rect) lds_append_row<TB>(PlL, a.k, (const TB*)a.PL, kp1, j);
+        }
+        op_forward(Lb + (long long)j * a.ldl);
+        if (j == 0) reduce_partials<SK>(a, a.cpart, inv_c, tile, a.c);
+        if (a.lam > 0.0) reduce_partials<SK>(a, a.fpart, inv_f, tile, a.F + (long long)j * a.s);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
+        for (int q = threadIdx.x; q < *pm.count; q += NT) pvD[pm.list_c[q]] = wt[pm.list_e[q]];
+        sketch_partial<TB, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart, tile);
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+        // ---- phase B: coefficients and elimination against the data-space basis
+        if (a.pmode == 1) {
+            lds_load_block<TB>(PlD, a.k, PDc, kp1, nh);
+            __syncthreads();
+        }
+        if (threadIdx.x < 64) forward_subst<TB>(PlD, a.k, pvD, nh, h_l);
+        __syncthreads();
+        if (tile == 0)
+            for (int i = threadIdx.x; i < nh; i += NT) a.H[(long long)j * kp1 + i] = h_l[i];
+        eliminate<TB, EPT>(acc, gm, Db, ldd, h_l, nh);
+        zero_pivots<EPT>(acc, vm, pm.bits);
+        tile_argmax<EPT>(acc, gm, vm, a.amv, a.ami, tile);
+        reduce_partials<SK>(a, a.zpart, inv_z, tile, a.Z + (long long)j * a.s);
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+        // ---- phase C: pivot, normalise, store
+        double hv;
+        int p;
+        global_argmax(a.amv, a.ami, 0, G, hv, p);
+        if (p == -2) { fail(-4); return; }
+        if (hv == 0.0 || j + 1 >= a.m) {                 // breakdown (or the space is exhausted)
+            if (tile == 0 && threadIdx.x == 0) a.H[(long long)j * kp1 + j + 1] = 0.0;
+            finish(j + 1, (j + 1 < a.k) ? 1 : 0, j + 1, rect ? j + 1 : 0);
+            return;
+        }
+        if (tile == 0 && threadIdx.x == 0) {
+            a.H[(long long)j * kp1 + j + 1] = hv;
+            a.tp[j + 1] = p;
+        }
+        TB* dst = Db + (long long)(j + 1) * ldd;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if ((vm >> i) & 1u) dst[gm[i]] = (TB)(acc[i] / hv);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        add_pivot<TB>(a.spm, tile, p, j + 1, pm, PD, kp1, Db, ldd);
+
+        if (!rect) {
+            if (a.lam > 0.0 && j + 1 < a.k) {
+#pragma unroll
+                for (int i = 0; i < EPT; ++i) {
+                    const int e = threadIdx.x + i * NT;
+                    if (e < tm.E) wt[e] = ((vm >> i) & 1u) ? (double)(TB)(acc[i] / hv) : 0.0;
+                }
+                __syncthreads();
+                sketch_partial<TB, SK>(a, wt, a.spm, tm, 1u, a.scf, sk, a.fpart, tile);
+            }
+            if (j + 1 == a.k) { finish(a.k, 0, a.k + 1, 0); return; }
+            if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+            continue;
+        }
+
+        // ---------------- sLSLU: adjoint half step ----------------
+        if (j + 1 == a.k) { finish(a.k, 0, a.k + 1, a.k); return; }   // l_{k+1} is not needed for x_k
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+        // ---- phase TA: q = A^T d_{j+1} on the n-tile
+        op_adjoint(Db + (long long)(j + 1) * ldd);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) acc[i] = ((vn >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
+        for (int q = threadIdx.x; q < *pn.count; q += NT) pvL[pn.list_c[q]] = wt[pn.list_e[q]];
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+        // ---- phase TB: coefficients W(1:j+1, j+2) and elimination against L
+        if (a.pmode == 1) {
+            lds_load_block<TB>(PlL, a.k, (const TB*)a.PL, kp1, nh);
+            __syncthreads();
+        }
+        if (threadIdx.x < 64) forward_subst<TB>(PlL, a.k, pvL, nh, h_l);
+        __syncthreads();
+        if (tile == 0)
+            for (int i = threadIdx.x; i < nh; i += NT) a.W[(long long)(j + 1) * a.k + i] = h_l[i];
+        eliminate<TB, EPT>(acc, gn, Lb, a.ldl, h_l, nh);
+        zero_pivots<EPT>(acc, vn, pn.bits);
+        tile_argmax<EPT>(acc, gn, vn, a.amv, a.ami, tile);
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+
+        // ---- phase TC: pivot of L, normalise, store, sketch S1 l_{j+1}
+        double wv;
+        int g;
+        global_argmax(a.amv, a.ami, 0, G, wv, g);
+        if (g == -2) { fail(-4); return; }
+        if (wv == 0.0 || j + 1 >= a.n) { finish(j + 1, 1, j + 2, j + 1); return; }
+        if (tile == 0 && threadIdx.x == 0) {
+            a.W[(long long)(j + 1) * a.k + j + 1] = wv;
+            a.gp[j + 1] = g;
+        }
+        TB* ldst = Lb + (long long)(j + 1) * a.ldl;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if ((vn >> i) & 1u) ldst[gn[i]] = (TB)(acc[i] / wv);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        add_pivot<TB>(a.spn, tile, g, j + 1, pn, PL, kp1, Lb, a.ldl);
+        if (a.lam > 0.0) {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) {
+                const int e = threadIdx.x + i * NT;
+                if (e < tn.E) wt[e] = ((vn >> i) & 1u) ? (double)(TB)(acc[i] / wv) : 0.0;
+            }
+            __syncthreads();
+            sketch_partial<TB, SK>(a, wt, a.spn, tn, 1u, a.scf, sk, a.fpart, tile);
+        }
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+    }
+}
+
+
+}  // namespace hk

@@ -1,0 +1,161 @@
+// Internal definitions shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hk {
+
+constexpr int NT = 512;             // threads per workgroup (8 wave64s)
+constexpr int NWAVE = NT / 64;
+constexpr int KMAX = 255;           // largest k: k+1 pivot slots fit 4 per lane of one wave
+constexpr int KSLOT = 4;            // (KMAX+1)/64
+constexpr int MAX_EPT = 4;          // elements per thread of a tile (tile <= 2048 elements)
+constexpr int MAXG = 256;           // workgroups of the persistent kernel (one per CU)
+
+enum OpKind { OP_BLUR = 0, OP_CSR = 1, OP_BLUR_ONEBAR = 2 };
+
+// Fixed-point scale 2^e such that terms whose magnitudes sum to at most
+// `bound` accumulate below 2^61 in int64 (exact, order-independent sums).
+__host__ __device__ inline double fx_scale(double bound)
+{
+    int ex = 0;
+    if (!(bound > 0.0)) return 1.0;
+    frexp(bound, &ex);
+    return ldexp(1.0, 61 - ex);
+}
+enum SketchKind { SK_GAUSS = 0, SK_SPARSE = 1 };
+
+// How the elements of one space (length m or n) are split into tiles, one
+// tile per workgroup.  kind 0: 2-D image tiles TY x TX (row-major image of
+// nx columns); kind 1: contiguous ranges [t*len/ntile, (t+1)*len/ntile).
+struct Space {
+    int kind;
+    int len;
+    int ntile;
+    int ny, nx, TY, TX, ntx;
+};
+
+// Device control block at the start of the workspace: status words, then
+// the grid-barrier counters, each on its own 256-byte line.
+struct alignas(256) CtlLine {
+    unsigned v;
+    unsigned pad[63];
+};
+
+struct Ctl {
+    unsigned bar;        // flat arrivals (start-up barrier)
+    unsigned abort;      // set when a barrier wait times out
+    int k_done;          // basis columns built
+    int status;          // 0 ok, 1 breakdown, <0 error (hk_status)
+    int ls_status;       // small least-squares status
+    int nt;              // pivots found in the data-space basis (t)
+    int ng;              // pivots found in the unknowns' basis (g, sLSLU)
+    int nbar;            // grid barriers passed (trace length / 2)
+    int pad[56];
+    CtlLine gcnt;        // XCD-leader arrivals
+    CtlLine xcnt[16];    // arrivals per XCD
+    CtlLine xflag[16];   // release epoch per XCD
+    CtlLine pop[16];     // workgroups per XCD
+};
+
+// Everything the persistent Hessenberg kernel needs (passed by value).
+struct KArgs {
+    int m, n, k, s, zeta;
+    double lam;
+    uint32_t seed_lo, seed_hi;
+    int rect;                   // 1: generalized Hessenberg (sLSLU)
+    int xcd_map;                // XCD-aware tile numbering
+    int G;                      // workgroups = tiles
+    const void* b;
+    Space spm, spn;             // tiling of the data space (m) and unknowns (n)
+    // blur
+    int ny, nx, r, bc;
+    const double* taps_y;
+    const double* taps_x;
+    // CSR of A (m rows) and of A^T (n rows)
+    const int64_t* rp;  const int* ci;  const void* cv;
+    const int64_t* rpt; const int* cit; const void* cvt;
+    int lpr, lprt;              // lanes per row for the two CSR products
+    // fixed-point scales 2^sc for the sparse-sign partial sums
+    double scz, scf;            // w = A l (|w| <= ||A||_inf), l (|l| <= 1)
+    // workspace
+    void* L; int64_t ldl;       // basis L: n x (k+1), column stride ldl
+    void* D; int64_t ldd;       // basis D: m x (k+1) (sLSLU)
+    double* H; double* W;       // (k+1) x k, k x k
+    int* tp; int* gp;           // pivots of D (or of L for sCMRH) and of L (sLSLU)
+    void* PD; void* PL;         // pivot blocks (k+1)^2, column-major, storage type
+    double* pvD; double* pvL;   // operator output at the pivot rows
+    double* amv; int* ami;      // argmax partials [2G]
+    long long* zpart;           // sketch partial sums [G*s] (int64 fixed point or FP64 bits)
+    long long* fpart;
+    long long* cpart;
+    double* Z; double* F; double* c;
+    Ctl* ctl;
+    unsigned long long timeout_ticks;
+    // optional per-barrier timestamps of workgroup 0 (wall clock ticks):
+    // trace[2e] before arriving at barrier e, trace[2e+1] after it released
+    unsigned long long* trace;
+    int trace_cap;
+    // pivot blocks in LDS: pmode 0 keeps a packed copy of every block for the
+    // whole solve (one row appended per step), pmode 1 bulk-loads the needed
+    // triangle into one LDS buffer before each substitution
+    int pmode;
+    // LDS layout (byte offsets into the dynamic shared buffer)
+    int lds_h, lds_w, lds_pl_m, lds_pc_m, lds_bm_m, lds_pl_n, lds_pc_n, lds_bm_n;
+    int lds_sk, lds_stage, lds_vert, lds_taps, lds_pD, lds_pL, lds_total;
+    // single-barrier blur kernel: FP64 scales 1/eta of the stored (unnormalised)
+    // basis vectors, window partial sums of A v at the pivots, layout
+    double* scale;              // k+1
+    double* wpart;              // (k+1) * nslot
+    int nslot, spx;             // slots per pivot, slots per row of the window box
+    int lds_scale, lds_hs, lds_wred;
+    int lds_skt;                // sparse-sign tables (0: built on the fly)
+};
+
+// Column-packed strict lower triangle of a (k+1) x (k+1) pivot block:
+// column c holds rows c+1..k.
+__host__ __device__ inline int packed_col(int c, int k) { return c * k - (c * (c - 1)) / 2; }
+__host__ __device__ inline long long packed_size(int k) { return (long long)k * (k + 1) / 2; }
+
+struct LsArgs {
+    int s, k;
+    double lam;
+    const double* Z; const double* F; const double* c;
+    double* Q; double* R; double* r; double* y; double* res; double* d;
+    Ctl* ctl;
+};
+
+struct CombineArgs {
+    int n, k;
+    const void* L; int64_t ldl;
+    const double* y;
+    const double* scale;         // per-column scale of the stored basis, or null
+    void* x;
+    const Ctl* ctl;
+};
+
+struct ApplyArgs {
+    int transpose;
+    Space sp;                    // output-space tiling
+    int ny, nx, r, bc;
+    const double* taps_y; const double* taps_x;
+    const int64_t* rp; const int* ci; const void* cv;
+    int lpr;
+    const void* x; void* y;
+    int lds_w, lds_stage, lds_vert, lds_taps, lds_total;
+};
+
+// Host-side launchers (defined in hk_kernels.hip).  Types: 0 f64, 1 f32;
+// tb = basis storage, to = operator / vector storage.
+hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KArgs& a, hipStream_t st);
+hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st);
+hipError_t launch_small_ls(const LsArgs& a, hipStream_t st);
+hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st);
+hipError_t launch_apply(int dtype, int op, int ept, const ApplyArgs& a, hipStream_t st);
+hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double* scale, int64_t len,
+                              int ncols, void* dst, hipStream_t st);
+hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int lds_bytes, int* blocks_per_cu);
+size_t small_ls_lds_bytes(int s, int k, double lam);
+
+}  // namespace hk

@@ -1,0 +1,290 @@
+// Non-iterative kernels (small least squares, combine, control reset,
+// standalone operator products) and the host-side launchers.
+#include "hk_device.hpp"
+
+namespace hk {
+
+// ------------------------------------------------------------------------
+// small sketched least squares, one workgroup:
+//   min_y ||c - Z y||^2 + lam^2 ||F y||^2,  M = [Z; lam F]
+// Classical Gram-Schmidt with one reorthogonalisation pass (CGS2) builds
+// M = Q R column by column; the right-hand side is projected column by
+// column, so res[j] is the minimised objective with the first j+1 columns.
+// ------------------------------------------------------------------------
+constexpr int LS_NT = 1024;
+constexpr int LS_NW = LS_NT / 64;
+
+__device__ double block_sum_ls(double v, double* red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < LS_NW; ++w) t += red[w];
+    return t;
+}
+
+__global__ __launch_bounds__(LS_NT) void small_ls_kernel(LsArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[LS_NW];
+    for (int i = threadIdx.x; i < a.k; i += LS_NT) a.res[i] = 0.0;
+    if (a.ctl->status < 0) return;
+    const int kd = a.ctl->k_done;
+    if (kd <= 0) return;
+    const int s = a.s;
+    const bool tik = a.lam > 0.0;
+    const int rows = tik ? 2 * s : s;
+    double* av = (double*)smem;           // rows
+    double* coef = av + rows;             // k
+    double* Q = a.Q;                      // rows x k
+    double* R = a.R;                      // k x k, column-major
+    double* r = a.r;                      // rows: residual of the right-hand side
+
+    for (int i = threadIdx.x; i < rows; i += LS_NT) r[i] = (i < s) ? a.c[i] : 0.0;
+    for (int i = threadIdx.x; i < a.k * a.k; i += LS_NT) R[i] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < kd; ++j) {
+        for (int i = threadIdx.x; i < rows; i += LS_NT)
+            av[i] = (i < s) ? a.Z[(long long)j * s + i] : a.lam * a.F[(long long)j * s + (i - s)];
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int c = wave; c < j; c += LS_NW) {
+                const double* qc = Q + (long long)c * rows;
+                double d = 0.0;
+                for (int i = lane; i < rows; i += 64) d = fma(qc[i], av[i], d);
+                d = wave_sum(d);
+                if (lane == 0) coef[c] = d;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < rows; i += LS_NT) {
+                double t = av[i];
+                for (int c = 0; c < j; ++c) t = fma(-Q[(long long)c * rows + i], coef[c], t);
+                av[i] = t;
+            }
+            for (int c = threadIdx.x; c < j; c += LS_NT) R[(long long)j * a.k + c] += coef[c];
+            __syncthreads();
+        }
+        double nn = 0.0;
+        for (int i = threadIdx.x; i < rows; i += LS_NT) nn = fma(av[i], av[i], nn);
+        const double nrm = sqrt(block_sum_ls(nn, red));
+        if (!(nrm > 0.0) || !isfinite(nrm)) {
+            if (threadIdx.x == 0) { a.ctl->ls_status = -4; a.ctl->status = -4; }
+            return;
+        }
+        if (threadIdx.x == 0) R[(long long)j * a.k + j] = nrm;
+        double dd = 0.0;
+        for (int i = threadIdx.x; i < rows; i += LS_NT) {
+            const double q = av[i] / nrm;
+            Q[(long long)j * rows + i] = q;
+            dd = fma(q, r[i], dd);
+        }
+        const double dj = block_sum_ls(dd, red);
+        double rr = 0.0;
+        for (int i = threadIdx.x; i < rows; i += LS_NT) {
+            const double t = fma(-dj, Q[(long long)j * rows + i], r[i]);
+            r[i] = t;
+            rr = fma(t, t, rr);
+        }
+        const double rn = sqrt(block_sum_ls(rr, red));
+        if (threadIdx.x == 0) { a.d[j] = dj; a.res[j] = rn; }
+        __syncthreads();
+    }
+    // back substitution R y = d by wave 0, column-oriented, d staged in LDS
+    for (int i = threadIdx.x; i < kd; i += LS_NT) coef[i] = a.d[i];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        for (int i = kd - 1; i >= 0; --i) {
+            const double yi = coef[i] / R[(long long)i * a.k + i];
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) a.y[i] = yi;
+            for (int q = lane; q < i; q += 64) coef[q] = fma(-R[(long long)i * a.k + q], yi, coef[q]);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (threadIdx.x == 0) a.ctl->ls_status = 0;
+}
+
+// ------------------------------------------------------------------------
+// x = L_k y (FP64 accumulation, columns in increasing order)
+// ------------------------------------------------------------------------
+template <typename TB, typename TO>
+__global__ __launch_bounds__(256) void combine_kernel(CombineArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const TB* L = (const TB*)a.L;
+    TO* x = (TO*)a.x;
+    const int st = a.ctl->status;
+    const int kd = (st < 0) ? 0 : a.ctl->k_done;
+    double acc = 0.0;
+    if (a.scale) {
+        for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], a.y[j] * a.scale[j], acc);
+    } else {
+        for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], a.y[j], acc);
+    }
+    x[i] = (TO)acc;
+}
+
+__global__ void ctl_init_kernel(Ctl* ctl)
+{
+    unsigned* w = (unsigned*)ctl;
+    for (unsigned i = threadIdx.x; i < sizeof(Ctl) / sizeof(unsigned); i += blockDim.x) w[i] = 0u;
+}
+
+// ------------------------------------------------------------------------
+// standalone operator product y = A x or A^T x (tiles of the output space)
+// ------------------------------------------------------------------------
+template <typename TS, int OP>
+__global__ __launch_bounds__(NT) void apply_kernel(ApplyArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* wt = (double*)(smem + a.lds_w);
+    TS* stage = (TS*)(smem + a.lds_stage);
+    double* vert = (double*)(smem + a.lds_vert);
+    double* taps = (double*)(smem + a.lds_taps);
+    const Tile ti = tile_info(a.sp, blockIdx.x);
+    if constexpr (OP == OP_BLUR) {
+        for (int q = threadIdx.x; q < 2 * a.r + 1; q += NT) {
+            taps[q] = a.taps_y[q];
+            taps[2 * a.r + 1 + q] = a.taps_x[q];
+        }
+        __syncthreads();
+        blur_tile<TS>((const TS*)a.x, a.ny, a.nx, a.r, a.bc, ti, a.sp.TY, a.sp.TX, taps,
+                      taps + 2 * a.r + 1, stage, vert, wt);
+    } else {
+        csr_tile<TS, TS>(a.rp, a.ci, (const TS*)a.cv, (const TS*)a.x, ti, a.lpr, wt);
+    }
+    TS* y = (TS*)a.y;
+    for (int e = threadIdx.x; e < ti.E; e += NT) {
+        int gi;
+        if (elem_global(a.sp, ti, e, gi)) y[gi] = (TS)wt[e];
+    }
+}
+
+// ------------------------------------------------------------------------
+// host launchers
+// ------------------------------------------------------------------------
+const void* select_iterate_f64(int op, int sketch, int ept);
+const void* select_iterate_f32(int op, int sketch, int ept);
+const void* select_iterate_mix(int op, int sketch, int ept);
+const void* select_blur_f64(int sketch, int ept);
+const void* select_blur_f32(int sketch, int ept);
+const void* select_blur_mix(int sketch, int ept);
+
+// basis storage / operator storage: (f64, f64), (f32, f32), (f64, f32)
+// op = OP_BLUR_ONEBAR selects the single-barrier blur kernel
+static const void* select_iterate(int tb, int to, int op, int sketch, int ept)
+{
+    if (op == OP_BLUR_ONEBAR) {
+        if (tb == 0 && to == 0) return select_blur_f64(sketch, ept);
+        if (tb == 1 && to == 1) return select_blur_f32(sketch, ept);
+        if (tb == 0 && to == 1) return select_blur_mix(sketch, ept);
+        return nullptr;
+    }
+    if (tb == 0 && to == 0) return select_iterate_f64(op, sketch, ept);
+    if (tb == 1 && to == 1) return select_iterate_f32(op, sketch, ept);
+    if (tb == 0 && to == 1) return select_iterate_mix(op, sketch, ept);
+    return nullptr;
+}
+
+hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int lds_bytes, int* blocks_per_cu)
+{
+    const void* f = select_iterate(tb, to, op, sketch, ept);
+    if (!f) return hipErrorInvalidValue;
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, NT, lds_bytes);
+}
+
+hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KArgs& a, hipStream_t st)
+{
+    const void* f = select_iterate(tb, to, op, sketch, ept);
+    if (f && a.lds_total > 65536) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_total);
+        if (e != hipSuccess) return e;
+    }
+    if (!f) return hipErrorInvalidValue;
+    KArgs args = a;
+    void* kargs[] = {&args};
+    return hipLaunchCooperativeKernel(f, dim3(a.G), dim3(NT), kargs, (unsigned)a.lds_total, st);
+}
+
+hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(256), 0, st, ctl);
+    return hipGetLastError();
+}
+
+size_t small_ls_lds_bytes(int s, int k, double lam)
+{
+    const int rows = lam > 0.0 ? 2 * s : s;
+    return sizeof(double) * (size_t)(rows + k);
+}
+
+hipError_t launch_small_ls(const LsArgs& a, hipStream_t st)
+{
+    const size_t lds = small_ls_lds_bytes(a.s, a.k, a.lam);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)small_ls_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(small_ls_kernel, dim3(1), dim3(LS_NT), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st)
+{
+    const int blocks = (a.n + 255) / 256;
+    if (tb == 0 && to == 0) hipLaunchKernelGGL((combine_kernel<double, double>), dim3(blocks), dim3(256), 0, st, a);
+    else if (tb == 1 && to == 1) hipLaunchKernelGGL((combine_kernel<float, float>), dim3(blocks), dim3(256), 0, st, a);
+    else if (tb == 0 && to == 1) hipLaunchKernelGGL((combine_kernel<double, float>), dim3(blocks), dim3(256), 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// dst[j * len + i] = scale[j] * src[j * ld + i] (normalised copy of a basis)
+template <typename TB>
+__global__ __launch_bounds__(256) void scale_basis_kernel(const TB* src, int64_t ld, const double* scale,
+                                                          int64_t len, TB* dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= len) return;
+    const double s = scale ? scale[j] : 1.0;
+    dst[(int64_t)j * len + i] = (TB)(s * (double)src[(int64_t)j * ld + i]);
+}
+
+hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double* scale, int64_t len,
+                              int ncols, void* dst, hipStream_t st)
+{
+    const dim3 grid((unsigned)((len + 255) / 256), (unsigned)ncols);
+    if (tb == 0)
+        hipLaunchKernelGGL(scale_basis_kernel<double>, grid, dim3(256), 0, st, (const double*)src, ld, scale, len, (double*)dst);
+    else
+        hipLaunchKernelGGL(scale_basis_kernel<float>, grid, dim3(256), 0, st, (const float*)src, ld, scale, len, (float*)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(int dtype, int op, int ept, const ApplyArgs& a, hipStream_t st)
+{
+    (void)ept;
+    const dim3 grid(a.sp.ntile), block(NT);
+    const unsigned lds = (unsigned)a.lds_total;
+    if (dtype == 0) {
+        if (op == OP_BLUR) hipLaunchKernelGGL((apply_kernel<double, OP_BLUR>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((apply_kernel<double, OP_CSR>), grid, block, lds, st, a);
+    } else {
+        if (op == OP_BLUR) hipLaunchKernelGGL((apply_kernel<float, OP_BLUR>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((apply_kernel<float, OP_CSR>), grid, block, lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hk

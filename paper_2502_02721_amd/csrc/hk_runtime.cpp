@@ -1,0 +1,962 @@
+// Host runtime of the C ABI in include/hk.h: handles, argument validation,
+// tiling and LDS layout, workspace, and the stream-ordered launch sequence
+//   control-block reset -> persistent basis iteration -> small sketched
+//   least squares -> x = L_k y.
+#include "hk.h"
+#include "hk_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace hk;
+
+namespace {
+
+thread_local std::string g_err;
+
+hk_status fail(hk_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(HK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct hk_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int ncu = 0;
+    size_t lds_max = 65536;
+    unsigned long long wall_rate_khz = 100000;
+};
+
+struct hk_op {
+    hk_context* ctx = nullptr;
+    int kind = OP_BLUR;
+    int64_t m = 0, n = 0;
+    int dtype = HK_F64;
+    // blur
+    int ny = 0, nx = 0, r = 0, bc = 0;
+    double* d_taps = nullptr;          // taps_y then taps_x
+    // CSR
+    int64_t nnz = 0;
+    int64_t* d_rp = nullptr;
+    int* d_ci = nullptr;
+    void* d_cv = nullptr;
+    int64_t* d_rpt = nullptr;
+    int* d_cit = nullptr;
+    void* d_cvt = nullptr;
+    int lpr = 16, lprt = 16;
+    double anorm = 0.0;                // ||A||_inf (max absolute row sum)
+    double anorm_t = 0.0;              // ||A^T||_inf
+};
+
+struct hk_solve {
+    hk_op* op = nullptr;
+    hk_params prm{};
+    int tb = HK_F64;               // basis storage type
+    int rect = 0;
+    int sk = SK_GAUSS;
+    int kernel = OP_BLUR;
+    int ept = 1;
+    int G = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    KArgs ka{};
+    LsArgs la{};
+    CombineArgs ca{};
+    static constexpr int NEV = 256;        // runs whose events are kept
+    hipEvent_t ev[NEV][3] = {};
+    long long runs = 0;                    // runs launched
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;   // of the last run
+    bool ran = false;
+    bool waited = false;
+    hk_status last = HK_OK;
+    int k_done = 0;
+    int nt = 0, ng = 0;
+};
+
+namespace {
+
+size_t dsize(int dtype) { return dtype == HK_F64 ? 8 : 4; }
+
+int lanes_per_row(double avg_nnz)
+{
+    int l = 4;
+    while (l < 64 && l * 4 < avg_nnz) l *= 2;
+    return l;
+}
+
+// ---------------------------------------------------------------- tiling
+struct Plan {
+    Space spm{}, spn{};
+    int kernel = OP_BLUR;   // OP_BLUR_ONEBAR, OP_BLUR (generic) or OP_CSR
+    int nslot = 0, spx = 0;
+    int G = 0;
+    int ept = 1;
+    int lds_total = 0;
+    KArgs lds{};      // only the lds_* fields
+    bool ok = false;
+    std::string why;
+};
+
+int lds_layout(KArgs& a, int kp1, int s, int ept, int rect, int op, int TY, int TX, int r, int dtype,
+               int pmode)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 16);
+        return (int)o;
+    };
+    a.lds_h = take(sizeof(double) * (KMAX + 1));
+    a.lds_w = take(sizeof(double) * NT * ept);
+    a.lds_pl_m = take(sizeof(int) * kp1);
+    a.lds_pc_m = take(sizeof(int) * kp1);
+    a.lds_bm_m = take(sizeof(unsigned) * ((NT * ept + 31) / 32));
+    if (rect) {
+        a.lds_pl_n = take(sizeof(int) * kp1);
+        a.lds_pc_n = take(sizeof(int) * kp1);
+        a.lds_bm_n = take(sizeof(unsigned) * ((NT * ept + 31) / 32));
+    } else {
+        a.lds_pl_n = a.lds_pl_m;
+        a.lds_pc_n = a.lds_pc_m;
+        a.lds_bm_n = a.lds_bm_m;
+    }
+    const size_t ng = (size_t)(s + 3) / 4;
+    a.lds_sk = take(sizeof(double) * std::max<size_t>((size_t)s, 4 * ng));
+    if (op == OP_BLUR) {
+        const int SW = TX + 2 * r, SH = TY + 2 * r;
+        a.lds_stage = take(dsize(dtype) * (size_t)SW * SH);
+        a.lds_vert = take(sizeof(double) * (size_t)TY * SW);
+        a.lds_taps = take(sizeof(double) * 2 * (2 * r + 1));
+    } else {
+        a.lds_stage = a.lds_vert = a.lds_taps = 0;
+    }
+    const size_t tri = dsize(dtype) * (size_t)packed_size(kp1 - 1);
+    a.pmode = pmode;
+    a.lds_pD = take(tri);
+    a.lds_pL = (rect && pmode == 0) ? take(tri) : a.lds_pD;
+    a.lds_total = (int)off;
+    return a.lds_total;
+}
+
+int kp1_of(const hk_params* p) { return p->k + 1; }
+
+// slots per pivot of the window partial sums: tiles a (2r+1)-wide window spans
+int spx_of(int r, int TX) { return (2 * r + 1 + TX - 1) / TX + 1; }
+int nslot_of(int r, int TY, int TX) { return spx_of(r, TX) * ((2 * r + 1 + TY - 1) / TY + 1); }
+
+// LDS of the single-barrier blur kernel; 0 if it does not fit.
+int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, int tb, int zeta, size_t lds_max)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 16);
+        return (int)o;
+    };
+    const int kp1 = k + 1;
+    a.lds_h = take(sizeof(double) * (KMAX + 1));
+    a.lds_hs = take(sizeof(double) * (KMAX + 1));
+    a.lds_scale = take(sizeof(double) * 2 * (KMAX + 1));
+    a.lds_w = take(sizeof(double) * NT * ept);
+    a.lds_pl_m = take(sizeof(int) * kp1);
+    a.lds_pc_m = take(sizeof(int) * kp1);
+    a.lds_bm_m = take(sizeof(unsigned) * ((NT * ept + 31) / 32));
+    a.lds_pl_n = take(sizeof(int) * kp1);      // all pivots
+    a.lds_pc_n = take(sizeof(int) * kp1);      // window list
+    a.lds_bm_n = a.lds_bm_m;
+    const size_t ng = (size_t)(s + 3) / 4;
+    a.lds_sk = take(sizeof(double) * std::max<size_t>((size_t)s, 4 * ng));
+    const int SW = TX + 2 * r, SH = TY + 2 * r;
+    a.lds_stage = take(dsize(tb) * (size_t)SW * SH);
+    a.lds_vert = take(sizeof(double) * (size_t)TY * SW);
+    a.lds_taps = take(sizeof(double) * 2 * (2 * r + 1));
+    a.lds_wred = take(sizeof(double) * (size_t)kp1 * (size_t)std::max(NWAVE, 1 + nslot_of(r, TY, TX)));
+    a.lds_pD = take(dsize(tb) * (size_t)packed_size(k));
+    a.lds_pL = a.lds_pD;
+    a.pmode = 0;
+    a.lds_skt = 0;
+    if (off > lds_max) return 0;
+    // sparse-sign tables of S2 and S1 (16 bits per nonzero) when they fit
+    const size_t tabs = sizeof(unsigned short) * 2 * (size_t)TY * TX * (size_t)zeta;
+    if (zeta > 0 && align_up(off + tabs, 16) <= lds_max) a.lds_skt = take(tabs);
+    a.lds_total = (int)off;
+    return a.lds_total;
+}
+
+Space range_space(int64_t len, int G)
+{
+    Space sp{};
+    sp.kind = 1;
+    sp.len = (int)len;
+    sp.ntile = G;
+    return sp;
+}
+
+Plan plan_solve(const hk_op* op, const hk_params* p, int rect, int max_blocks, size_t lds_max)
+{
+    Plan pl;
+    const int tb = p->basis_dtype;
+    // pivot blocks: a persistent LDS copy of each if they fit, else one
+    // buffer loaded before each substitution
+    auto layout = [&](int ept, int TY, int TX, int r, int opk) {
+        lds_layout(pl.lds, kp1_of(p), p->s, ept, rect, opk, TY, TX, r, tb, 0);
+        if ((size_t)pl.lds.lds_total > lds_max)
+            lds_layout(pl.lds, kp1_of(p), p->s, ept, rect, opk, TY, TX, r, tb, 1);
+        pl.lds_total = pl.lds.lds_total;
+    };
+    const int kp1 = p->k + 1;
+    const int G_cap = std::max(1, std::min(max_blocks, MAXG));
+    if (op->kind == OP_BLUR) {
+        // 2-D tiles: area ~ n / #CU rounded to a power of two, >= 64
+        const int64_t n = op->n;
+        int64_t area = 64;
+        while (area * G_cap < n) area *= 2;
+        for (; area <= (int64_t)NT * MAX_EPT; area *= 2) {
+            int lg = 0;
+            while ((int64_t(1) << (lg + 1)) <= area) ++lg;
+            int TX = 1 << ((lg + 1) / 2), TY = 1 << (lg / 2);
+            TX = std::min<int>(TX, std::max(1, op->nx));
+            while ((int64_t)TX * TY < area && TY < op->ny) TY *= 2;
+            const int ntx = (op->nx + TX - 1) / TX, nty = (op->ny + TY - 1) / TY;
+            const int G = ntx * nty;
+            if (G > G_cap) continue;
+            Space sp{};
+            sp.kind = 0; sp.len = (int)n; sp.ntile = G;
+            sp.ny = op->ny; sp.nx = op->nx; sp.TY = TY; sp.TX = TX; sp.ntx = ntx;
+            pl.spm = pl.spn = sp;
+            pl.G = G;
+            pl.ept = (TY * TX + NT - 1) / NT;
+            if (pl.ept > 2) pl.ept = 4;
+            if (lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, tb,
+                                  p->sketch == HK_SKETCH_SPARSE_SIGN ? p->zeta : 0, lds_max)) {
+                pl.kernel = OP_BLUR_ONEBAR;
+                pl.lds_total = pl.lds.lds_total;
+                pl.spx = spx_of(op->r, TX);
+                pl.nslot = nslot_of(op->r, TY, TX);
+            } else {
+                pl.kernel = OP_BLUR;
+                layout(pl.ept, TY, TX, op->r, OP_BLUR);
+            }
+            pl.ok = true;
+            return pl;
+        }
+        pl.why = "image too large for one tile per compute unit";
+        return pl;
+    }
+    // CSR: contiguous row ranges; both spaces share the workgroup count
+    const int64_t lmax = rect ? std::max(op->m, op->n) : op->m;
+    const int64_t lmin = rect ? std::min(op->m, op->n) : op->m;
+    int G = (int)std::min<int64_t>(G_cap, lmin);
+    if (G >= 8) G -= G % 8;
+    const int64_t per = (lmax + G - 1) / G;
+    if (per > (int64_t)NT * MAX_EPT) {
+        pl.why = "operator too large for one tile per compute unit";
+        return pl;
+    }
+    pl.G = G;
+    pl.kernel = OP_CSR;
+    pl.spm = range_space(op->m, G);
+    pl.spn = rect ? range_space(op->n, G) : pl.spm;
+    pl.ept = (int)((per + NT - 1) / NT);
+    if (pl.ept > 2) pl.ept = 4;
+    layout(pl.ept, 0, 0, 0, OP_CSR);
+    pl.ok = true;
+    return pl;
+}
+
+hk_status validate(const hk_op* op, const hk_params* p, int* rect)
+{
+    if (!op || !p) return fail(HK_EINVAL, "null operator or parameters");
+    if (p->flags & ~(uint32_t)HK_FLAG_TRACE) return fail(HK_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->k < 1) return fail(HK_EINVAL, "k must be >= 1 (got %d)", p->k);
+    if (p->k > KMAX) return fail(HK_EUNSUPPORTED, "k = %d exceeds the supported maximum %d", p->k, KMAX);
+    if (p->k > std::min(op->m, op->n)) return fail(HK_EINVAL, "k = %d exceeds min(m, n)", p->k);
+    if (p->s < p->k + 1) return fail(HK_EINVAL, "sketch size s = %d must be >= k + 1 = %d", p->s, p->k + 1);
+    if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(HK_EINVAL, "lambda must be finite and >= 0");
+    if (p->sketch != HK_SKETCH_GAUSSIAN && p->sketch != HK_SKETCH_SPARSE_SIGN)
+        return fail(HK_EINVAL, "unknown sketch type %d", p->sketch);
+    if (p->sketch == HK_SKETCH_SPARSE_SIGN && (p->zeta < 1 || p->zeta > p->s))
+        return fail(HK_EINVAL, "zeta = %d must be in [1, s]", p->zeta);
+    if (p->s > 16384) return fail(HK_EUNSUPPORTED, "sketch size s = %d exceeds 16384", p->s);
+    if (p->basis_dtype != HK_F64 && p->basis_dtype != HK_F32)
+        return fail(HK_EINVAL, "unknown basis dtype %d", p->basis_dtype);
+    if (p->basis_dtype == HK_F32 && op->dtype == HK_F64)
+        return fail(HK_EUNSUPPORTED, "FP32 bases need an FP32 operator");
+    int r = 0;
+    if (p->method == HK_METHOD_AUTO) r = (op->m != op->n);
+    else if (p->method == HK_METHOD_HESSENBERG) r = 0;
+    else if (p->method == HK_METHOD_CHANGING_HESSENBERG) r = 1;
+    else return fail(HK_EINVAL, "unknown method %d", p->method);
+    if (!r && op->m != op->n) return fail(HK_EINVAL, "the Hessenberg method needs a square operator");
+    if (r && op->kind != OP_CSR)
+        return fail(HK_EUNSUPPORTED, "the generalized Hessenberg method needs A^T: use a CSR operator");
+    *rect = r;
+    return HK_OK;
+}
+
+struct WsLayout {
+    size_t ctl, L, D, H, W, tp, gp, PD, PL, pvD, pvL, amv, ami, zpart, fpart, cpart, Z, F, c;
+    size_t Q, R, r, y, res, d, trace, scale, wpart, total;
+    int trace_cap;
+    int64_t ldl, ldd;
+};
+
+WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nslot)
+{
+    WsLayout w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const int k = p->k, kp1 = k + 1, s = p->s;
+    const size_t es = dsize(p->basis_dtype);
+    w.ldl = (int64_t)align_up((size_t)op->n, 64);
+    w.ldd = (int64_t)align_up((size_t)op->m, 64);
+    const int rows = p->lambda > 0.0 ? 2 * s : s;
+    w.ctl = take(sizeof(Ctl));
+    w.L = take(es * (size_t)w.ldl * kp1);
+    w.D = rect ? take(es * (size_t)w.ldd * kp1) : 0;
+    w.H = take(sizeof(double) * (size_t)kp1 * k);
+    w.W = take(sizeof(double) * (size_t)k * k);
+    w.tp = take(sizeof(int) * kp1);
+    w.gp = take(sizeof(int) * kp1);
+    w.PD = rect ? take(es * (size_t)kp1 * kp1) : 0;
+    w.PL = take(es * (size_t)kp1 * kp1);
+    w.pvD = take(sizeof(double) * kp1);
+    w.pvL = take(sizeof(double) * kp1);
+    w.amv = take(sizeof(double) * 2 * G);
+    w.ami = take(sizeof(int) * 2 * G);
+    w.zpart = take(sizeof(long long) * 2 * (size_t)G * s);     // two parities
+    w.fpart = take(sizeof(long long) * 2 * (size_t)G * s);
+    w.cpart = take(sizeof(long long) * (size_t)G * s);
+    w.Z = take(sizeof(double) * (size_t)s * k);
+    w.F = take(sizeof(double) * (size_t)s * k);
+    w.c = take(sizeof(double) * s);
+    w.Q = take(sizeof(double) * (size_t)rows * k);
+    w.R = take(sizeof(double) * (size_t)k * k);
+    w.r = take(sizeof(double) * rows);
+    w.y = take(sizeof(double) * k);
+    w.res = take(sizeof(double) * k);
+    w.d = take(sizeof(double) * k);
+    w.trace_cap = (p->flags & HK_FLAG_TRACE) ? 2 * (6 * kp1 + 8) + 16 * (kp1 + 1) : 0;
+    w.trace = take(sizeof(unsigned long long) * (size_t)std::max(1, w.trace_cap));
+    w.scale = take(sizeof(double) * kp1);
+    w.wpart = take(sizeof(double) * 2 * (size_t)kp1 * std::max(1, nslot));
+    w.total = off;
+    return w;
+}
+
+hk_status current_device(hk_context* ctx)
+{
+    HIP_TRY(hipSetDevice(ctx->device));
+    return HK_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int32_t hk_abi_version(void) { return HK_ABI_VERSION; }
+
+const char* hk_last_error(void) { return g_err.c_str(); }
+
+hk_status hk_context_create(int32_t device, void* stream, hk_context** out)
+{
+    if (!out) return fail(HK_EINVAL, "null output handle");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(HK_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    auto* c = new (std::nothrow) hk_context;
+    if (!c) return fail(HK_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->ncu = prop.multiProcessorCount;
+    c->lds_max = prop.sharedMemPerBlock;
+    int rate = 0;
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
+        c->wall_rate_khz = (unsigned long long)rate;
+    *out = c;
+    return HK_OK;
+}
+
+hk_status hk_context_destroy(hk_context* ctx)
+{
+    if (!ctx) return fail(HK_EINVAL, "null context");
+    delete ctx;
+    return HK_OK;
+}
+
+static void op_free(hk_op* op)
+{
+    if (!op) return;
+    hipFree(op->d_taps);
+    hipFree(op->d_rp);
+    hipFree(op->d_ci);
+    hipFree(op->d_cv);
+    hipFree(op->d_rpt);
+    hipFree(op->d_cit);
+    hipFree(op->d_cvt);
+    delete op;
+}
+
+hk_status hk_op_create_blur(hk_context* ctx, int64_t ny, int64_t nx, const double* taps_y,
+                            const double* taps_x, int32_t radius, hk_bc bc, hk_dtype dt, hk_op** out)
+{
+    if (!out) return fail(HK_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!ctx || !taps_y || !taps_x) return fail(HK_EINVAL, "null argument");
+    if (ny < 1 || nx < 1 || ny * nx > (int64_t)1 << 30) return fail(HK_EINVAL, "bad image size %lld x %lld", (long long)ny, (long long)nx);
+    if (radius < 0 || radius > 64) return fail(HK_EINVAL, "radius %d outside [0, 64]", radius);
+    if (bc != HK_BC_ZERO && bc != HK_BC_REFLECT) return fail(HK_EINVAL, "unknown boundary condition %d", bc);
+    if (dt != HK_F64 && dt != HK_F32) return fail(HK_EINVAL, "unknown dtype %d", dt);
+    if (bc == HK_BC_REFLECT && (radius > ny || radius > nx))
+        return fail(HK_EINVAL, "reflective boundary needs radius <= image size");
+    double sy = 0.0, sx = 0.0;
+    for (int i = 0; i <= 2 * radius; ++i) {
+        if (!std::isfinite(taps_y[i]) || !std::isfinite(taps_x[i])) return fail(HK_ENUMERIC, "non-finite PSF tap");
+        sy += std::fabs(taps_y[i]);
+        sx += std::fabs(taps_x[i]);
+    }
+    hk_status st = current_device(ctx);
+    if (st) return st;
+    auto* op = new (std::nothrow) hk_op;
+    if (!op) return fail(HK_ENOMEM, "host allocation failed");
+    op->ctx = ctx;
+    op->kind = OP_BLUR;
+    op->m = op->n = ny * nx;
+    op->dtype = dt;
+    op->ny = (int)ny; op->nx = (int)nx; op->r = radius; op->bc = bc;
+    op->anorm = op->anorm_t = sy * sx;
+    const size_t nt = 2 * (size_t)radius + 1;
+    if (hipMalloc(&op->d_taps, sizeof(double) * 2 * nt) != hipSuccess) { op_free(op); return fail(HK_ENOMEM, "hipMalloc failed"); }
+    std::vector<double> taps(2 * nt);
+    std::copy(taps_y, taps_y + nt, taps.begin());
+    std::copy(taps_x, taps_x + nt, taps.begin() + nt);
+    if (hipMemcpy(op->d_taps, taps.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice) != hipSuccess) {
+        op_free(op);
+        return fail(HK_EDEVICE, "hipMemcpy failed");
+    }
+    *out = op;
+    return HK_OK;
+}
+
+hk_status hk_op_create_gaussian_blur(hk_context* ctx, int64_t ny, int64_t nx, double sigma,
+                                     int32_t radius, hk_bc bc, hk_dtype dt, hk_op** out)
+{
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(HK_EINVAL, "sigma must be positive");
+    if (radius < 0 || radius > 64) return fail(HK_EINVAL, "radius %d outside [0, 64]", radius);
+    std::vector<double> g(2 * (size_t)radius + 1);
+    double sum = 0.0;
+    for (int a = -radius; a <= radius; ++a) {
+        g[a + radius] = std::exp(-(double)a * a / (2.0 * sigma * sigma));
+        sum += g[a + radius];
+    }
+    for (double& v : g) v /= sum;
+    return hk_op_create_blur(ctx, ny, nx, g.data(), g.data(), radius, bc, dt, out);
+}
+
+hk_status hk_op_create_csr(hk_context* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                           const int32_t* col, const void* val, hk_dtype dt, hk_op** out)
+{
+    if (!out) return fail(HK_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!ctx || !rowptr || (nnz > 0 && (!col || !val))) return fail(HK_EINVAL, "null argument");
+    if (m < 1 || n < 1 || m >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31) || nnz < 0)
+        return fail(HK_EINVAL, "bad CSR shape m=%lld n=%lld nnz=%lld", (long long)m, (long long)n, (long long)nnz);
+    if (dt != HK_F64 && dt != HK_F32) return fail(HK_EINVAL, "unknown dtype %d", dt);
+    if (rowptr[0] != 0 || rowptr[m] != nnz) return fail(HK_EINVAL, "rowptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < m; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return fail(HK_EINVAL, "rowptr decreases at row %lld", (long long)i);
+    for (int64_t p = 0; p < nnz; ++p)
+        if (col[p] < 0 || col[p] >= n) return fail(HK_EINVAL, "column index out of range at %lld", (long long)p);
+    const size_t es = dsize(dt);
+    auto valat = [&](int64_t p) -> double {
+        return dt == HK_F64 ? ((const double*)val)[p] : (double)((const float*)val)[p];
+    };
+    // A^T by counting sort (stable: row order within each column)
+    std::vector<int64_t> rpt(n + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) rpt[col[p] + 1]++;
+    for (int64_t c = 0; c < n; ++c) rpt[c + 1] += rpt[c];
+    std::vector<int32_t> cit(nnz);
+    std::vector<unsigned char> cvt(es * (size_t)nnz);
+    std::vector<int64_t> fill(rpt.begin(), rpt.end() - 1);
+    double anorm = 0.0;
+    std::vector<double> colsum(n, 0.0);
+    for (int64_t i = 0; i < m; ++i) {
+        double rs = 0.0;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const double v = valat(p);
+            if (!std::isfinite(v)) return fail(HK_ENUMERIC, "non-finite matrix entry at %lld", (long long)p);
+            rs += std::fabs(v);
+            colsum[col[p]] += std::fabs(v);
+            const int64_t q = fill[col[p]]++;
+            cit[q] = (int32_t)i;
+            std::memcpy(&cvt[es * q], (const unsigned char*)val + es * p, es);
+        }
+        anorm = std::max(anorm, rs);
+    }
+    double anorm_t = 0.0;
+    for (double v : colsum) anorm_t = std::max(anorm_t, v);
+
+    hk_status st = current_device(ctx);
+    if (st) return st;
+    auto* op = new (std::nothrow) hk_op;
+    if (!op) return fail(HK_ENOMEM, "host allocation failed");
+    op->ctx = ctx;
+    op->kind = OP_CSR;
+    op->m = m; op->n = n; op->nnz = nnz; op->dtype = dt;
+    op->anorm = anorm; op->anorm_t = anorm_t;
+    op->lpr = lanes_per_row((double)nnz / (double)m);
+    op->lprt = lanes_per_row((double)nnz / (double)n);
+    const size_t nb = std::max<int64_t>(nnz, 1);
+    bool ok = hipMalloc(&op->d_rp, sizeof(int64_t) * (m + 1)) == hipSuccess &&
+              hipMalloc(&op->d_ci, sizeof(int32_t) * nb) == hipSuccess &&
+              hipMalloc(&op->d_cv, es * nb) == hipSuccess &&
+              hipMalloc(&op->d_rpt, sizeof(int64_t) * (n + 1)) == hipSuccess &&
+              hipMalloc(&op->d_cit, sizeof(int32_t) * nb) == hipSuccess &&
+              hipMalloc(&op->d_cvt, es * nb) == hipSuccess;
+    if (!ok) { op_free(op); return fail(HK_ENOMEM, "hipMalloc failed for the CSR arrays"); }
+    ok = hipMemcpy(op->d_rp, rowptr, sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(op->d_rpt, rpt.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && nnz > 0)
+        ok = hipMemcpy(op->d_ci, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(op->d_cv, val, es * nnz, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(op->d_cit, cit.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(op->d_cvt, cvt.data(), es * nnz, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) { op_free(op); return fail(HK_EDEVICE, "hipMemcpy failed for the CSR arrays"); }
+    *out = op;
+    return HK_OK;
+}
+
+hk_status hk_op_shape(const hk_op* op, int64_t* m, int64_t* n)
+{
+    if (!op) return fail(HK_EINVAL, "null operator");
+    if (m) *m = op->m;
+    if (n) *n = op->n;
+    return HK_OK;
+}
+
+hk_status hk_op_apply(hk_op* op, int32_t transpose, const void* x_dev, void* y_dev)
+{
+    if (!op || !x_dev || !y_dev) return fail(HK_EINVAL, "null argument");
+    if (transpose && op->kind != OP_CSR) return fail(HK_EUNSUPPORTED, "A^T products are provided for CSR operators");
+    hk_status st = current_device(op->ctx);
+    if (st) return st;
+    ApplyArgs a{};
+    a.transpose = transpose;
+    a.x = x_dev;
+    a.y = y_dev;
+    int ept = 1;
+    if (op->kind == OP_BLUR) {
+        Space sp{};
+        sp.kind = 0; sp.len = (int)op->n; sp.ny = op->ny; sp.nx = op->nx;
+        sp.TX = std::min(32, op->nx);
+        sp.TY = 16;
+        sp.ntx = (op->nx + sp.TX - 1) / sp.TX;
+        sp.ntile = sp.ntx * ((op->ny + sp.TY - 1) / sp.TY);
+        a.sp = sp;
+        a.ny = op->ny; a.nx = op->nx; a.r = op->r; a.bc = op->bc;
+        a.taps_y = op->d_taps;
+        a.taps_x = op->d_taps + 2 * op->r + 1;
+        size_t off = 0;
+        auto take = [&](size_t b) { size_t o = off; off = align_up(off + b, 16); return (int)o; };
+        const int SW = sp.TX + 2 * op->r, SH = sp.TY + 2 * op->r;
+        a.lds_w = take(sizeof(double) * sp.TY * sp.TX);
+        a.lds_stage = take(dsize(op->dtype) * (size_t)SW * SH);
+        a.lds_vert = take(sizeof(double) * (size_t)sp.TY * SW);
+        a.lds_taps = take(sizeof(double) * 2 * (2 * op->r + 1));
+        a.lds_total = (int)off;
+        if ((size_t)a.lds_total > op->ctx->lds_max) return fail(HK_EUNSUPPORTED, "blur radius too large for LDS");
+    } else {
+        const int64_t len = transpose ? op->n : op->m;
+        const int per = 256;
+        Space sp = range_space(len, (int)((len + per - 1) / per));
+        a.sp = sp;
+        a.rp = transpose ? op->d_rpt : op->d_rp;
+        a.ci = transpose ? op->d_cit : op->d_ci;
+        a.cv = transpose ? op->d_cvt : op->d_cv;
+        a.lpr = transpose ? op->lprt : op->lpr;
+        a.lds_w = 0;
+        a.lds_total = (int)(sizeof(double) * per);
+    }
+    HIP_TRY(launch_apply(op->dtype, op->kind, ept, a, op->ctx->stream));
+    return HK_OK;
+}
+
+hk_status hk_op_destroy(hk_op* op)
+{
+    if (!op) return fail(HK_EINVAL, "null operator");
+    hipSetDevice(op->ctx->device);
+    op_free(op);
+    return HK_OK;
+}
+
+static hk_status max_blocks(const hk_op* op, const hk_params* p, int rect, Plan* out)
+{
+    // probe occupancy with the LDS of the plan at #CU blocks; shrink if needed
+    const hk_context* ctx = op->ctx;
+    Plan pl = plan_solve(op, p, rect, ctx->ncu, ctx->lds_max);
+    if (!pl.ok) return fail(HK_EUNSUPPORTED, "%s", pl.why.c_str());
+    if ((size_t)pl.lds_total > ctx->lds_max)
+        return fail(HK_EUNSUPPORTED, "LDS need %d B exceeds the device limit %zu B", pl.lds_total, ctx->lds_max);
+    int per_cu = 0;
+    hipError_t e = iterate_occupancy(p->basis_dtype, op->dtype, pl.kernel,
+                                     p->sketch == HK_SKETCH_SPARSE_SIGN ? SK_SPARSE : SK_GAUSS, pl.ept,
+                                     pl.lds_total, &per_cu);
+    if (e != hipSuccess) return fail(HK_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
+    if (per_cu < 1) return fail(HK_EUNSUPPORTED, "the basis kernel does not fit on a compute unit");
+    if (pl.G > per_cu * ctx->ncu) return fail(HK_EUNSUPPORTED, "grid of %d exceeds co-resident capacity", pl.G);
+    *out = pl;
+    return HK_OK;
+}
+
+hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* p, size_t* bytes)
+{
+    if (!bytes) return fail(HK_EINVAL, "null output");
+    int rect = 0;
+    hk_status st = validate(op, p, &rect);
+    if (st) return st;
+    Plan pl = plan_solve(op, p, rect, op->ctx->ncu, op->ctx->lds_max);
+    if (!pl.ok) return fail(HK_EUNSUPPORTED, "%s", pl.why.c_str());
+    *bytes = ws_layout(op, p, rect, pl.G, pl.nslot).total;
+    return HK_OK;
+}
+
+hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
+{
+    if (!out) return fail(HK_EINVAL, "null output handle");
+    *out = nullptr;
+    int rect = 0;
+    hk_status st = validate(op, p, &rect);
+    if (st) return st;
+    st = current_device(op->ctx);
+    if (st) return st;
+    Plan pl;
+    st = max_blocks(op, p, rect, &pl);
+    if (st) return st;
+    const WsLayout w = ws_layout(op, p, rect, pl.G, pl.nslot);
+    auto* sv = new (std::nothrow) hk_solve;
+    if (!sv) return fail(HK_ENOMEM, "host allocation failed");
+    sv->op = op;
+    sv->prm = *p;
+    sv->tb = p->basis_dtype;
+    sv->rect = rect;
+    sv->sk = p->sketch == HK_SKETCH_SPARSE_SIGN ? SK_SPARSE : SK_GAUSS;
+    sv->ept = pl.ept;
+    sv->kernel = pl.kernel;
+    sv->G = pl.G;
+    if (hipMalloc(&sv->ws, w.total) != hipSuccess) {
+        delete sv;
+        return fail(HK_ENOMEM, "hipMalloc of %zu workspace bytes failed", w.total);
+    }
+    sv->ws_bytes = w.total;
+    for (int i = 0; i < hk_solve::NEV; ++i)
+        for (int q = 0; q < 3; ++q)
+            if (hipEventCreate(&sv->ev[i][q]) != hipSuccess) {
+                hk_solve_destroy(sv);
+                return fail(HK_EDEVICE, "hipEventCreate failed");
+            }
+    // zero the workspace once (H, W, pivots read back even when unused)
+    if (hipMemset(sv->ws, 0, w.total) != hipSuccess) {
+        hk_solve_destroy(sv);
+        return fail(HK_EDEVICE, "hipMemset failed");
+    }
+    unsigned char* base = (unsigned char*)sv->ws;
+    KArgs& a = sv->ka;
+    a = pl.lds;    // lds_* offsets
+    a.m = (int)op->m; a.n = (int)op->n; a.k = p->k; a.s = p->s; a.zeta = p->zeta;
+    a.lam = p->lambda;
+    a.seed_lo = (uint32_t)(p->seed & 0xffffffffu);
+    a.seed_hi = (uint32_t)(p->seed >> 32);
+    a.rect = rect;
+    a.G = pl.G;
+    a.xcd_map = (pl.G % 8 == 0) ? 1 : 0;
+    a.spm = pl.spm;
+    a.spn = pl.spn;
+    a.ny = op->ny; a.nx = op->nx; a.r = op->r; a.bc = op->bc;
+    a.taps_y = op->d_taps;
+    a.taps_x = op->d_taps ? op->d_taps + 2 * op->r + 1 : nullptr;
+    a.rp = op->d_rp; a.ci = op->d_ci; a.cv = op->d_cv;
+    a.rpt = op->d_rpt; a.cit = op->d_cit; a.cvt = op->d_cvt;
+    a.lpr = op->lpr; a.lprt = op->lprt;
+    a.scz = fx_scale((double)op->m * op->anorm * 1.000001);
+    a.scf = fx_scale((double)op->n * 1.000001);
+    a.L = base + w.L; a.ldl = w.ldl;
+    a.D = rect ? base + w.D : nullptr; a.ldd = w.ldd;
+    a.H = (double*)(base + w.H);
+    a.W = (double*)(base + w.W);
+    a.tp = (int*)(base + w.tp);
+    a.gp = (int*)(base + w.gp);
+    a.PD = rect ? base + w.PD : nullptr;
+    a.PL = base + w.PL;
+    a.pvD = (double*)(base + w.pvD);
+    a.pvL = (double*)(base + w.pvL);
+    a.amv = (double*)(base + w.amv);
+    a.ami = (int*)(base + w.ami);
+    a.zpart = (long long*)(base + w.zpart);
+    a.fpart = (long long*)(base + w.fpart);
+    a.cpart = (long long*)(base + w.cpart);
+    a.Z = (double*)(base + w.Z);
+    a.F = (double*)(base + w.F);
+    a.c = (double*)(base + w.c);
+    a.ctl = (Ctl*)(base + w.ctl);
+    a.timeout_ticks = op->ctx->wall_rate_khz * 1000ull * 5ull;   // 5 s per barrier wait
+    a.scale = (double*)(base + w.scale);
+    a.wpart = (double*)(base + w.wpart);
+    a.nslot = pl.nslot;
+    a.spx = pl.spx;
+    a.trace_cap = w.trace_cap;
+    a.trace = w.trace_cap ? (unsigned long long*)(base + w.trace) : nullptr;
+    LsArgs& l = sv->la;
+    l.s = p->s; l.k = p->k; l.lam = p->lambda;
+    l.Z = a.Z; l.F = a.F; l.c = a.c;
+    l.Q = (double*)(base + w.Q);
+    l.R = (double*)(base + w.R);
+    l.r = (double*)(base + w.r);
+    l.y = (double*)(base + w.y);
+    l.res = (double*)(base + w.res);
+    l.d = (double*)(base + w.d);
+    l.ctl = a.ctl;
+    CombineArgs& c = sv->ca;
+    c.n = (int)op->n; c.k = p->k; c.L = a.L; c.ldl = a.ldl; c.y = l.y; c.ctl = a.ctl;
+    c.scale = (pl.kernel == OP_BLUR_ONEBAR) ? a.scale : nullptr;
+    if ((size_t)small_ls_lds_bytes(p->s, p->k, p->lambda) > op->ctx->lds_max) {
+        hk_solve_destroy(sv);
+        return fail(HK_EUNSUPPORTED, "sketch size too large for the least-squares kernel's LDS");
+    }
+    *out = sv;
+    return HK_OK;
+}
+
+hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
+{
+    if (!sv || !b_dev || !x_dev) return fail(HK_EINVAL, "null argument");
+    hk_status st = current_device(sv->op->ctx);
+    if (st) return st;
+    hipStream_t s = sv->op->ctx->stream;
+    KArgs a = sv->ka;
+    a.b = b_dev;
+    const int slot = (int)(sv->runs % hk_solve::NEV);
+    sv->ev0 = sv->ev[slot][0];
+    sv->ev1 = sv->ev[slot][1];
+    sv->ev2 = sv->ev[slot][2];
+    HIP_TRY(launch_ctl_init(a.ctl, s));
+    HIP_TRY(hipEventRecord(sv->ev0, s));
+    HIP_TRY(launch_iterate(sv->tb, sv->op->dtype, sv->kernel, sv->sk, sv->ept, a, s));
+    HIP_TRY(hipEventRecord(sv->ev1, s));
+    HIP_TRY(launch_small_ls(sv->la, s));
+    CombineArgs c = sv->ca;
+    c.x = x_dev;
+    HIP_TRY(launch_combine(sv->tb, sv->op->dtype, c, s));
+    HIP_TRY(hipEventRecord(sv->ev2, s));
+    sv->runs++;
+    sv->ran = true;
+    sv->waited = false;
+    return HK_OK;
+}
+
+hk_status hk_solve_wait(hk_solve* sv)
+{
+    if (!sv) return fail(HK_EINVAL, "null solve");
+    if (!sv->ran) return fail(HK_EINVAL, "the solve has not been run");
+    if (sv->waited) return sv->last;
+    hk_status st = current_device(sv->op->ctx);
+    if (st) return st;
+    HIP_TRY(hipEventSynchronize(sv->ev2));
+    Ctl ctl;
+    HIP_TRY(hipMemcpy(&ctl, sv->ka.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    sv->waited = true;
+    sv->k_done = ctl.k_done;
+    sv->nt = ctl.nt;
+    sv->ng = ctl.ng;
+    if (ctl.abort) sv->last = fail(HK_EDEVICE, "grid barrier timed out: the basis kernel was aborted");
+    else if (ctl.status < 0) sv->last = fail(ctl.status, ctl.status == HK_ENUMERIC ? "non-finite values or a rank-deficient sketched problem" : "device error %d", ctl.status);
+    else sv->last = ctl.status;
+    return sv->last;
+}
+
+static hk_status ensure_done(hk_solve* sv)
+{
+    if (!sv) return fail(HK_EINVAL, "null solve");
+    hk_status st = hk_solve_wait(sv);
+    return st < 0 ? st : HK_OK;
+}
+
+hk_status hk_solve_info(hk_solve* sv, int32_t* k_done)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    if (k_done) *k_done = sv->k_done;
+    return sv->last;
+}
+
+hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    const int k = sv->prm.k;
+    if (H) HIP_TRY(hipMemcpy(H, sv->ka.H, sizeof(double) * (size_t)(k + 1) * k, hipMemcpyDeviceToHost));
+    if (W) {
+        if (!sv->rect) return fail(HK_EINVAL, "W exists for the generalized Hessenberg method only");
+        HIP_TRY(hipMemcpy(W, sv->ka.W, sizeof(double) * (size_t)k * k, hipMemcpyDeviceToHost));
+    }
+    return HK_OK;
+}
+
+hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    const int k = sv->prm.k;
+    std::vector<int> buf(k + 1);
+    if (t) {
+        HIP_TRY(hipMemcpy(buf.data(), sv->ka.tp, sizeof(int) * (k + 1), hipMemcpyDeviceToHost));
+        for (int i = 0; i <= k; ++i) t[i] = i < sv->nt ? buf[i] : -1;
+    }
+    if (g) {
+        if (!sv->rect) return fail(HK_EINVAL, "g exists for the generalized Hessenberg method only");
+        HIP_TRY(hipMemcpy(buf.data(), sv->ka.gp, sizeof(int) * (k + 1), hipMemcpyDeviceToHost));
+        for (int i = 0; i < k; ++i) g[i] = i < sv->ng ? buf[i] : -1;
+    }
+    return HK_OK;
+}
+
+hk_status hk_solve_get_residuals(hk_solve* sv, double* res)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    if (!res) return fail(HK_EINVAL, "null output");
+    HIP_TRY(hipMemcpy(res, sv->la.res, sizeof(double) * sv->prm.k, hipMemcpyDeviceToHost));
+    for (int i = sv->k_done; i < sv->prm.k; ++i) res[i] = 0.0;
+    return HK_OK;
+}
+
+hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    const size_t sk = (size_t)sv->prm.s * sv->prm.k;
+    if (Z) HIP_TRY(hipMemcpy(Z, sv->ka.Z, sizeof(double) * sk, hipMemcpyDeviceToHost));
+    if (F) HIP_TRY(hipMemcpy(F, sv->ka.F, sizeof(double) * sk, hipMemcpyDeviceToHost));
+    if (c) HIP_TRY(hipMemcpy(c, sv->ka.c, sizeof(double) * sv->prm.s, hipMemcpyDeviceToHost));
+    return HK_OK;
+}
+
+hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    if (!dst_dev) return fail(HK_EINVAL, "null output");
+    const size_t es = dsize(sv->tb);
+    const int kp1 = sv->prm.k + 1;
+    if (which == 0 && sv->kernel == OP_BLUR_ONEBAR) {
+        // stored unnormalised with per-column scales: copy l_j = s_j v_j
+        HIP_TRY(launch_scale_basis(sv->tb, sv->ka.L, sv->ka.ldl, sv->ka.scale, sv->op->n, kp1, dst_dev,
+                                   sv->op->ctx->stream));
+        HIP_TRY(hipStreamSynchronize(sv->op->ctx->stream));
+    } else if (which == 0) {
+        HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->n, sv->ka.L, es * sv->ka.ldl, es * sv->op->n, kp1,
+                            hipMemcpyDeviceToDevice));
+    } else if (which == 1) {
+        if (!sv->rect) return fail(HK_EINVAL, "D exists for the generalized Hessenberg method only");
+        HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->m, sv->ka.D, es * sv->ka.ldd, es * sv->op->m, kp1,
+                            hipMemcpyDeviceToDevice));
+    } else {
+        return fail(HK_EINVAL, "which must be 0 (L) or 1 (D)");
+    }
+    return HK_OK;
+}
+
+hk_status hk_solve_timing(hk_solve* sv, double* iterate_ms, double* total_ms)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, sv->ev0, sv->ev1));
+    HIP_TRY(hipEventElapsedTime(&b, sv->ev0, sv->ev2));
+    if (iterate_ms) *iterate_ms = a;
+    if (total_ms) *total_ms = b;
+    return HK_OK;
+}
+
+hk_status hk_solve_timing_history(hk_solve* sv, int32_t max_runs, double* iterate_ms,
+                                  double* total_ms, int32_t* n)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    if (max_runs < 0 || !n) return fail(HK_EINVAL, "bad arguments");
+    const long long kept = std::min<long long>(sv->runs, hk_solve::NEV);
+    const int cnt = (int)std::min<long long>(kept, max_runs);
+    for (int i = 0; i < cnt; ++i) {
+        const long long run = sv->runs - cnt + i;
+        const int slot = (int)(run % hk_solve::NEV);
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, sv->ev[slot][0], sv->ev[slot][1]));
+        HIP_TRY(hipEventElapsedTime(&b, sv->ev[slot][0], sv->ev[slot][2]));
+        if (iterate_ms) iterate_ms[i] = a;
+        if (total_ms) total_ms[i] = b;
+    }
+    *n = cnt;
+    return HK_OK;
+}
+
+hk_status hk_solve_get_trace(hk_solve* sv, int32_t max, uint64_t* ticks, int32_t* n, double* tick_ns)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    if (!n || max < 0 || (max > 0 && !ticks)) return fail(HK_EINVAL, "bad arguments");
+    if (!sv->ka.trace) return fail(HK_EINVAL, "the solve was created without HK_FLAG_TRACE");
+    Ctl ctl;
+    HIP_TRY(hipMemcpy(&ctl, sv->ka.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    const int rec = sv->ka.trace_cap;   // barrier pairs, then sub-step marks (blur kernel)
+    const int cnt = std::min(rec, (int)max);
+    if (cnt > 0) HIP_TRY(hipMemcpy(ticks, sv->ka.trace, sizeof(uint64_t) * cnt, hipMemcpyDeviceToHost));
+    *n = cnt;
+    if (tick_ns) *tick_ns = 1e6 / (double)sv->op->ctx->wall_rate_khz;
+    return HK_OK;
+}
+
+hk_status hk_solve_destroy(hk_solve* sv)
+{
+    if (!sv) return fail(HK_EINVAL, "null solve");
+    hipSetDevice(sv->op->ctx->device);
+    for (int i = 0; i < hk_solve::NEV; ++i)
+        for (int q = 0; q < 3; ++q)
+            if (sv->ev[i][q]) hipEventDestroy(sv->ev[i][q]);
+    hipFree(sv->ws);
+    delete sv;
+    return HK_OK;
+}
+
+}  // extern "C"

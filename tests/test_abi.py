@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every function include/hk.h declares;
+argument validation that needs no GPU (CPU-only: no device work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hk.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hk_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def hk():
+    import paper_2502_02721_amd as hk
+    if not os.path.exists(hk.LIB_PATH):
+        from paper_2502_02721_amd import build
+        build.build()
+    return hk
+
+
+def test_header_lists_the_binding_functions(hk):
+    assert header_functions() == sorted(hk.ABI_FUNCTIONS)
+
+
+def test_library_exports_every_header_function(hk):
+    raw = C.CDLL(hk.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(raw, name), name
+
+
+def test_version_and_null_argument_errors(hk):
+    L = hk.lib()
+    assert hk.hk_abi_version() == 1
+    assert L.hk_solve_wait(None) == hk.HK_EINVAL
+    assert "null" in hk.hk_last_error()
+    assert L.hk_op_destroy(None) == hk.HK_EINVAL
+    assert L.hk_context_destroy(None) == hk.HK_EINVAL
+    assert L.hk_context_create(0, None, None) == hk.HK_EINVAL
+    assert L.hk_op_create_blur(None, 4, 4, None, None, 1, 0, 0, None) == hk.HK_EINVAL
+    assert L.hk_solve_create(None, None, None) == hk.HK_EINVAL
+
+
+def test_params_struct_layout(hk):
+    # matches the C struct: int32 k, s; double lambda; int32 sketch, zeta;
+    # uint64 seed; int32 method, basis_dtype; uint32 flags
+    assert C.sizeof(hk.hk_params) == 48
+    assert hk.hk_params.lambda_.offset == 8 and hk.hk_params.seed.offset == 24
