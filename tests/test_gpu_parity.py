@@ -1,0 +1,169 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64
+oracle on identical seeded inputs.
+
+Bars: pivot sequences bit-exact except at excused near-ties; relative
+solution error <= 1e-10 with FP64 storage and <= 1e-4 with FP32 storage;
+H, the sketches and the residual history agree on the common pivot prefix;
+operator products agree to rounding.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from hk_gpu import compare_solve, gpu_solve, random_csr, rel, rounded_problem, storage_np, tiny_blur
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_02721_amd as hk
+    hk.lib()   # raises if the library is not built: no fallback
+    return hk
+
+
+@pytest.fixture(scope="module")
+def ctx(hk):
+    return hk.Context(0)
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------- operators
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ny,nx,r,bc", [(64, 64, 7, W.BC_ZERO), (50, 70, 3, W.BC_REFLECT),
+                                        (37, 129, 15, W.BC_ZERO), (512, 512, 15, W.BC_REFLECT)])
+def test_blur_apply(hk, ctx, orc, dtype, ny, nx, r, bc):
+    import torch
+    _flush(f"blur apply {ny}x{nx} r={r} bc={bc} {dtype}")
+    P = tiny_blur(ny, nx, r / 3.5, r, bc, k=1, s=2, dtype=dtype)
+    from hk_gpu import make_operator
+    op = make_operator(hk, ctx, P)
+    x = np.random.default_rng(3).standard_normal(P.n).astype(storage_np(dtype))
+    y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+    ref = orc.Operator(P).apply(x.astype(np.float64))
+    tol = 1e-14 if dtype == "f64" else 1e-6
+    assert np.max(np.abs(y - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_csr_apply_and_transpose(hk, ctx, orc, dtype):
+    import torch
+    _flush(f"csr apply {dtype}")
+    P = random_csr(700, 333, 0.05, k=1, s=2, dtype=dtype)
+    from hk_gpu import make_operator
+    op = make_operator(hk, ctx, P)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(P.n).astype(storage_np(dtype))
+    z = rng.standard_normal(P.m).astype(storage_np(dtype))
+    O = orc.Operator(rounded_problem(P))
+    y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+    yt = op.apply(torch.tensor(z, device="cuda"), transpose=True).cpu().numpy().astype(np.float64)
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    assert rel(y, O.apply(x.astype(np.float64))) <= tol
+    assert rel(yt, O.apply_t(z.astype(np.float64))) <= tol
+
+
+# ---------------------------------------------------------------- sCMRH
+def _parity(hk, ctx, orc, P, method=0):
+    _flush(f"solve {P.name} m={P.m} n={P.n} k={P.k} s={P.s} lam={P.lam} sketch={P.sketch} {P.dtype}")
+    Pr = rounded_problem(P)
+    o = orc.solve(Pr, keep_basis=True, method=None if method == 0 else (0 if method == 1 else 1))
+    g = gpu_solve(hk, ctx, P, method=method)
+    err = compare_solve(Pr, g, o)
+    _flush(f"  rel x err {err:.3e}, k_done {g['k_done']}")
+    return g, o
+
+
+@pytest.mark.parametrize("name", ["c1", "c1_tik"])
+def test_scmrh_64x64_fp64(hk, ctx, orc, name):
+    _parity(hk, ctx, orc, W.config(name))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("sketch,lam", [(W.SKETCH_GAUSSIAN, 0.0), (W.SKETCH_SPARSE_SIGN, 0.0),
+                                        (W.SKETCH_GAUSSIAN, 1e-2), (W.SKETCH_SPARSE_SIGN, 1e-2)])
+def test_scmrh_ragged_image(hk, ctx, orc, dtype, sketch, lam):
+    # 50 x 70 image: several tiles with a ragged right and bottom edge
+    P = tiny_blur(50, 70, 1.5, 5, W.BC_REFLECT, k=25, s=60, lam=lam, sketch=sketch, zeta=5, dtype=dtype)
+    _parity(hk, ctx, orc, P)
+
+
+# ---------------------------------------------------------------- sLSLU
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("sketch,lam", [(W.SKETCH_GAUSSIAN, 0.0), (W.SKETCH_SPARSE_SIGN, 0.5)])
+@pytest.mark.parametrize("m,n", [(900, 613), (613, 900)])
+def test_slslu_random_csr(hk, ctx, orc, dtype, sketch, lam, m, n):
+    P = random_csr(m, n, 0.02, k=20, s=44, lam=lam, sketch=sketch, zeta=3, dtype=dtype)
+    _parity(hk, ctx, orc, P)
+
+
+def test_scmrh_on_square_csr(hk, ctx, orc):
+    P = random_csr(500, 500, 0.03, k=30, s=62, dtype="f64")
+    _parity(hk, ctx, orc, P, method=hk.HK_METHOD_HESSENBERG)
+
+
+# ---------------------------------------------------------------- edge cases
+def test_breakdown_invariant_subspace(hk, ctx, orc):
+    n = 300
+    A = np.diag(np.arange(1.0, n + 1))
+    b = np.zeros(n); b[123] = 2.0
+    P = W.dense_problem("diag", A, b, k=5, s=12)
+    g = gpu_solve(hk, ctx, P, method=hk.HK_METHOD_HESSENBERG)
+    assert g["status"] == hk.HK_BREAKDOWN and g["k_done"] == 1
+    x = np.zeros(n); x[123] = 2.0 / 124.0
+    assert rel(g["x"], x) <= 1e-14
+    assert g["t"][0] == 123 and np.all(g["t"][1:] == -1)
+
+
+def test_zero_rhs(hk, ctx):
+    P = tiny_blur(32, 32, 1.0, 3, W.BC_ZERO, k=4, s=10).replace(b=np.zeros(1024))
+    g = gpu_solve(hk, ctx, P)
+    assert g["k_done"] == 0 and np.all(g["x"] == 0) and g["status"] == hk.HK_BREAKDOWN
+
+
+def test_k_equals_n_exact_solve(hk, ctx):
+    n = 12
+    rng = np.random.default_rng(11)
+    A = np.eye(n) + 0.3 * rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    P = W.dense_problem("sq", A, b, k=n, s=n + 1)
+    g = gpu_solve(hk, ctx, P, method=hk.HK_METHOD_HESSENBERG)
+    assert g["k_done"] == n
+    assert rel(g["x"], np.linalg.solve(A, b)) <= 1e-10
+
+
+def test_repeat_runs_are_bitwise_identical(hk, ctx):
+    P = tiny_blur(64, 96, 2.0, 7, W.BC_REFLECT, k=30, s=62, lam=1e-3, sketch=W.SKETCH_SPARSE_SIGN,
+                  dtype="f32")
+    g = gpu_solve(hk, ctx, P, runs=3, keep_basis=False)
+    assert all(np.array_equal(g["xs"][0], x) for x in g["xs"][1:])
+
+
+def test_invalid_parameters_rejected(hk, ctx):
+    P = tiny_blur(16, 16, 1.0, 2, W.BC_ZERO, k=4, s=10)
+    from hk_gpu import make_operator
+    op = make_operator(hk, ctx, P)
+    for kw in [dict(k=0, s=10), dict(k=4, s=4), dict(k=4, s=10, lam=-1.0), dict(k=300, s=400),
+               dict(k=4, s=10, sketch=hk.HK_SKETCH_SPARSE_SIGN, zeta=11)]:
+        with pytest.raises(hk.HKError):
+            hk.Solve(op, **kw)
+    with pytest.raises(hk.HKError) as e:
+        hk.Solve(op, k=4, s=10, method=hk.HK_METHOD_CHANGING_HESSENBERG)
+    assert e.value.status == hk.HK_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------- full-size workloads
+def test_scmrh_512_fp32_sparse_sign(hk, ctx, orc):
+    # the full 512 x 512 deblurring workload (k = 100, s = 400, zeta = 8, lambda = 1e-2)
+    _parity(hk, ctx, orc, W.config("c2"))
+
+
+def test_slslu_tomography_fp32(hk, ctx, orc):
+    # the full 256 x 256 parallel-beam workload (180 x 362 rays, k = 150, s = 302)
+    _parity(hk, ctx, orc, W.config("c3"))
