@@ -1,0 +1,142 @@
+"""Benchmark: Hessenberg iterations per second of the sketched inner-product
+free Krylov solver on the 512 x 512 deblurring workload, on one MI355X.
+
+Workload (one "step" = one whole solve): 512 x 512 image (n = m = 262144),
+separable Gaussian blur sigma = 4 px, 31 x 31 stencil, reflective boundary,
+seeded piecewise-smooth phantom with 2% noise, k = 100 Hessenberg steps,
+sparse-sign sketch s = 400 with 8 nonzeros per column, Tikhonov lambda = 1e-2.
+FP32 storage of the operator input, b, x and the Krylov basis; FP64
+arithmetic.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `roofline` is for the dominant kernel (the persistent
+basis-iteration kernel): algorithmic bytes per launch (sum over steps j of
+(j + 1) basis vectors of n FP32 values: read L_j, write l_{j+1}) over its
+average launch duration from HIP events recorded on its stream during the
+timed region.  `cpu_baseline` times the CPU oracle on the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# FETCH_SIZE / WRITE_SIZE of the dominant kernel, KiB per dispatch, scaled by
+# the copy-kernel calibration; see the profiles/ summaries.  None until taken
+# for the current kernel.
+TRAFFIC_BYTES = None
+
+
+def algorithmic_bytes(n: int, k: int, w: int) -> int:
+    # step j (1..k) reads the j basis vectors l_1..l_j (l_j is also the operator
+    # input) and writes l_{j+1}: (j + 1) n w bytes.
+    return sum((j + 1) * n * w for j in range(1, k + 1))
+
+
+def cpu_baseline(P, max_seconds: float = 30.0):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    Pr = P.replace(b=P.b.astype(np.float32).astype(np.float64))
+    t0 = time.perf_counter()
+    o = oracle.solve(Pr)
+    dt = time.perf_counter() - t0
+    return {"value": o["k_done"] / dt, "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full solve of the same workload (k={o['k_done']}) in {dt:.2f} s, "
+                      "FP64, OpenMP over the operator loops"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c2", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2502_02721_amd as hk
+
+    P = W.config(args.workload)
+    tdt = np.float32 if P.dtype == "f32" else np.float64
+    bdt = hk.HK_F32 if P.basis_dtype == "f32" else hk.HK_F64
+    ctx = hk.Context(0)
+    dt = hk.HK_F32 if P.dtype == "f32" else hk.HK_F64
+    if P.kind == "blur":
+        op = hk.Operator.blur(ctx, P.ny, P.nx, P.taps_y, P.taps_x, P.radius, P.bc, dt)
+    else:
+        op = hk.Operator.csr(ctx, P.m, P.n, P.rowptr, P.col, P.val.astype(tdt), dt)
+    sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, basis_dtype=bdt)
+    b = torch.tensor(P.b.astype(tdt), device="cuda:0")
+    x = torch.empty(P.n, dtype=b.dtype, device="cuda:0")
+
+    for _ in range(args.warmup):
+        sv.run(b, x)
+    sv.wait()
+    torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} solves)", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sv.run(b, x)
+    st = sv.wait()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_done = sv.k_done()
+    it_ms, tot_ms = sv.timing_history(args.steps)
+    print(f"# timed {args.steps} solves in {wall:.4f} s, status {st}", file=sys.stderr, flush=True)
+
+    w = 4 if P.basis_dtype == "f32" else 8
+    ms_per_step = wall * 1e3 / args.steps
+    iters = k_done * args.steps
+    value = iters / wall
+    alg = algorithmic_bytes(P.n, k_done, w) if P.kind == "blur" else None
+    iter_avg = float(np.mean(it_ms))
+    roof = None
+    if alg is not None:
+        achieved = alg / (iter_avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": TRAFFIC_BYTES,
+                "kernel": "iterate_kernel (persistent basis iteration)",
+                "alg_bytes_per_launch": alg, "avg_launch_ms": round(iter_avg, 4)}
+    out = {
+        "metric": "Hessenberg iters/s + HBM GB/s at 512² deblur; solves/s with p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "Hessenberg iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "deblur-512x512 (n=262144), Gaussian blur sigma=4 31x31 reflective, "
+                               "k=100, sparse-sign s=400 zeta=8, lambda=1e-2",
+                   "storage": P.basis_dtype, "arithmetic": "f64", "k": k_done, "s": P.s,
+                   "parallelism": "single GPU, one persistent workgroup per tile"},
+        "solves_per_s": round(args.steps / wall, 2),
+        "hbm_gbs": round(alg / (ms_per_step * 1e-3) / 1e9, 1) if alg else None,
+        "latency_ms": {"p50": round(float(np.percentile(tot_ms, 50)), 4),
+                       "p99": round(float(np.percentile(tot_ms, 99)), 4)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(P)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
