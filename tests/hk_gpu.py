@@ -101,10 +101,32 @@ def col_rel(A, B):
     return float(np.max(np.linalg.norm(A - B, axis=0) / nb)) if A.size else 0.0
 
 
-def compare_solve(P, g, o):
+def sensitivity_bars(name):
+    """Bars for a workload whose FP64 result is itself rounding-sensitive,
+    from its fixture (tests/golden/<name>_sensitivity.json, written by
+    tests/golden/make_sensitivity.py from the oracle alone): one-ulp changes of
+    b move the oracle's own bases by up to `drift` column-relatively before the
+    pivots split, so a pivot tie closer than that and an intermediate
+    difference of that size are not decided by the arithmetic.  Twice the
+    largest drift seen is allowed."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_sensitivity.json")
+    with open(path) as f:
+        runs = json.load(f)["runs"]
+    basis = max(max(r["D_drift"], r["L_drift"]) for r in runs)
+    mid = max(max(r["H_drift"], r["Z_drift"]) for r in runs)
+    return {"tau": 2.0 * basis, "mid": 2.0 * mid}
+
+
+def compare_solve(P, g, o, bars=None):
     """Element-by-element comparison of a GPU solve with the oracle.  All
-    diagnostics are printed before any assertion."""
+    diagnostics are printed before any assertion.  `bars` may widen the
+    near-tie and intermediate bars of a rounding-sensitive workload (see
+    sensitivity_bars); the bar on x is always the class bar."""
     cls = P.dtype                      # precision class of the workload
+    tau = max(TAU[cls], (bars or {}).get("tau", 0.0))
+    mid = max(MID_TOL[cls], (bars or {}).get("mid", 0.0))
     kd = o["k_done"]
     err = rel(g["x"], o["x"])
     nL = o["Lmat"] if o["method"] == 0 else o["Dmat"]
@@ -128,18 +150,18 @@ def compare_solve(P, g, o):
     assert (g["status"] == 1) == (o["status"] == 1)
     assert err <= X_TOL[cls], f"relative solution error {err:.3e} > {X_TOL[cls]:.0e}"
     if i is not None:
-        assert near is not None and near <= TAU[cls], f"pivot {i} mismatch is not a near-tie ({near})"
+        assert near is not None and near <= tau, f"pivot {i} mismatch is not a near-tie ({near})"
     if o["method"] == 1:
         gg = [int(v) for v in g["g"] if v >= 0]
         j = first_mismatch(gg, [int(v) for v in o["g"]])
         if j is not None:
             assert j < len(gg) and j < o["Lmat"].shape[1]
             nearg = 1.0 - abs(o["Lmat"][gg[j], j])
-            assert nearg <= TAU[cls], f"pivot g{j} mismatch is not a near-tie ({nearg})"
-    assert eH <= MID_TOL[cls], f"H differs: {eH:.3e}"
-    assert ez <= MID_TOL[cls], f"Z differs: {ez:.3e}"
-    assert ef <= MID_TOL[cls], f"F differs: {ef:.3e}"
-    assert er <= MID_TOL[cls], f"residual history differs: {er:.3e}"
+            assert nearg <= tau, f"pivot g{j} mismatch is not a near-tie ({nearg})"
+    assert eH <= mid, f"H differs: {eH:.3e}"
+    assert ez <= mid, f"Z differs: {ez:.3e}"
+    assert ef <= mid, f"F differs: {ef:.3e}"
+    assert er <= mid, f"residual history differs: {er:.3e}"
     # S2 b depends on b only; FP32 bases generate the Gaussian entries in FP32
     assert ec <= (1e-13 if P.basis_dtype == "f64" else 1e-6), f"S2 b differs: {ec:.3e}"
     return err

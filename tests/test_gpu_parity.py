@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from hk_gpu import compare_solve, gpu_solve, random_csr, rel, rounded_problem, storage_np, tiny_blur
+from hk_gpu import sensitivity_bars, compare_solve, gpu_solve, random_csr, rel, rounded_problem, storage_np, tiny_blur
 
 pytestmark = pytest.mark.gpu
 
@@ -70,12 +70,12 @@ def test_csr_apply_and_transpose(hk, ctx, orc, dtype):
 
 
 # ---------------------------------------------------------------- sCMRH
-def _parity(hk, ctx, orc, P, method=0):
+def _parity(hk, ctx, orc, P, method=0, bars=None):
     _flush(f"solve {P.name} m={P.m} n={P.n} k={P.k} s={P.s} lam={P.lam} sketch={P.sketch} {P.dtype}")
     Pr = rounded_problem(P)
     o = orc.solve(Pr, keep_basis=True, method=None if method == 0 else (0 if method == 1 else 1))
     g = gpu_solve(hk, ctx, P, method=method)
-    err = compare_solve(Pr, g, o)
+    err = compare_solve(Pr, g, o, bars)
     _flush(f"  rel x err {err:.3e}, k_done {g['k_done']}")
     return g, o
 
@@ -165,5 +165,7 @@ def test_scmrh_512_fp32_sparse_sign(hk, ctx, orc):
 
 
 def test_slslu_tomography_fp32(hk, ctx, orc):
-    # the full 256 x 256 parallel-beam workload (180 x 362 rays, k = 150, s = 302)
-    _parity(hk, ctx, orc, W.config("c3"))
+    # the full 256 x 256 parallel-beam workload (180 x 362 rays, k = 150, s = 302);
+    # its FP64 result is rounding-sensitive, so the near-tie and intermediate
+    # bars come from the oracle's own one-ulp spread (x keeps the FP32 bar)
+    _parity(hk, ctx, orc, W.config("c3"), bars=sensitivity_bars("c3"))
