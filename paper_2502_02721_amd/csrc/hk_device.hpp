@@ -272,7 +272,7 @@ __device__ bool hbar_init(Ctl* ctl, BarState& bs, unsigned G, unsigned long long
     return s_ok != 0;
 }
 
-__device__ bool hbar_sync(Ctl* ctl, BarState& bs, unsigned long long timeout,
+__device__ __forceinline__ bool hbar_sync(Ctl* ctl, BarState& bs, unsigned long long timeout,
                           unsigned long long* trace = nullptr, int trace_cap = 0)
 {
     __shared__ int s_ok;
@@ -339,36 +339,46 @@ __device__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int b
     // vertical pass: each thread computes 4 consecutive rows of one column
     // from a sliding window of 4 staged values (one LDS read, 4 independent
     // FMAs per tap)
-    for (int it = threadIdx.x; it < (TY / 4) * SW; it += NT) {
+    // (TY need not be a multiple of 4: the last group clamps its reads to
+    // the staged rows and stores only the rows that exist)
+    const int ngy = (TY + 3) / 4;
+    for (int it = threadIdx.x; it < ngy * SW; it += NT) {
         const int g = it / SW, xx = it - g * SW;
-        const TS* col = stage + (4 * g) * SW + xx;
-        double s0 = (double)col[0], s1 = (double)col[SW], s2 = (double)col[2 * SW];
+        const int y0 = 4 * g;
+        const TS* col = stage + xx;
+        double s0 = (double)col[y0 * SW], s1 = (double)col[min(y0 + 1, SH - 1) * SW],
+               s2 = (double)col[min(y0 + 2, SH - 1) * SW];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         for (int b = 0; b < taps; ++b) {
-            const double s3 = (double)col[(b + 3) * SW];
+            const double s3 = (double)col[min(y0 + b + 3, SH - 1) * SW];
             const double w = tyl[b];
             a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, s3, a3);
             s0 = s1; s1 = s2; s2 = s3;
         }
-        double* vo = vert + (4 * g) * SW + xx;
-        vo[0] = a0; vo[SW] = a1; vo[2 * SW] = a2; vo[3 * SW] = a3;
+        double* vo = vert + y0 * SW + xx;
+        vo[0] = a0;
+        if (y0 + 1 < TY) vo[SW] = a1;
+        if (y0 + 2 < TY) vo[2 * SW] = a2;
+        if (y0 + 3 < TY) vo[3 * SW] = a3;
     }
     __syncthreads();
     if (tmk && threadIdx.x == 0) tmk[1] = wall_clock64();
-    // horizontal pass: 2 consecutive outputs of one row per thread
-    for (int it = threadIdx.x; it < TY * (TX / 2); it += NT) {
-        const int yy = it / (TX / 2), x2 = it - yy * (TX / 2);
-        const double* row = vert + yy * SW + 2 * x2;
-        double s0 = row[0];
+    // horizontal pass: 2 consecutive outputs of one row per thread (an odd
+    // TX clamps the last pair's extra read and drops its second output)
+    const int ngx = (TX + 1) / 2;
+    for (int it = threadIdx.x; it < TY * ngx; it += NT) {
+        const int yy = it / ngx, x0 = 2 * (it - yy * ngx);
+        const double* row = vert + yy * SW;
+        double s0 = row[x0];
         double a0 = 0.0, a1 = 0.0;
         for (int b = 0; b < taps; ++b) {
-            const double s1 = row[b + 1];
+            const double s1 = row[min(x0 + b + 1, SW - 1)];
             const double w = txl[b];
             a0 = fma(w, s0, a0); a1 = fma(w, s1, a1);
             s0 = s1;
         }
-        wt[yy * TX + 2 * x2] = a0;
-        wt[yy * TX + 2 * x2 + 1] = a1;
+        wt[yy * TX + x0] = a0;
+        if (x0 + 1 < TX) wt[yy * TX + x0 + 1] = a1;
     }
     __syncthreads();
 }
@@ -486,8 +496,11 @@ __device__ void sketch_gauss_partial(const double* vals, const Space& sp, const 
     __syncthreads();
 }
 
+constexpr unsigned short TAB_NONE = 0xFFFFu;
+
 // Sparse sign from a table built once per solve: tab[e * zeta + b] holds
-// (row << 1) | negative for block b of element e's column.
+// (row << 1) | negative for block b of element e's column; tab[e * zeta] is
+// TAB_NONE for tile slots outside the image.
 __device__ void sketch_sparse_partial_tab(const double* vals, const Tile& ti, int s, int zeta,
                                           const unsigned short* tab, double scale, long long* acc,
                                           long long* out)
@@ -495,9 +508,10 @@ __device__ void sketch_sparse_partial_tab(const double* vals, const Tile& ti, in
     for (int r = threadIdx.x; r < s; r += NT) acc[r] = 0;
     __syncthreads();
     for (int e = threadIdx.x; e < ti.E; e += NT) {
+        const unsigned short* te = tab + e * zeta;
+        if (te[0] == TAB_NONE) continue;
         const long long q = __double2ll_rn(vals[e] * scale);
         if (q == 0) continue;
-        const unsigned short* te = tab + e * zeta;
         for (int b = 0; b < zeta; ++b) {
             const unsigned ent = te[b];
             atomicAdd((unsigned long long*)&acc[ent >> 1], (unsigned long long)((ent & 1u) ? -q : q));
@@ -507,14 +521,17 @@ __device__ void sketch_sparse_partial_tab(const double* vals, const Tile& ti, in
     for (int r = threadIdx.x; r < s; r += NT) out[r] = acc[r];
 }
 
-// Build the table for the tile's elements (invalid elements get zero values
-// in vals, so their entries are never used).
+// Build the table for the tile's elements (rows < 2^14, so an entry never
+// equals TAB_NONE).
 __device__ void sketch_sparse_table(const Space& sp, const Tile& ti, int s, int zeta, uint32_t stream,
                                     uint32_t k0, uint32_t k1, unsigned short* tab)
 {
     for (int e = threadIdx.x; e < ti.E; e += NT) {
         int gi;
-        if (!elem_global(sp, ti, e, gi)) gi = 0;
+        if (!elem_global(sp, ti, e, gi)) {
+            tab[e * zeta] = TAB_NONE;
+            continue;
+        }
         for (int b4 = 0; b4 < zeta; b4 += 4) {
             const Words w = philox10((uint32_t)gi, (uint32_t)(b4 >> 2), stream, 1u, k0, k1);
 #pragma unroll
@@ -548,7 +565,7 @@ __device__ __forceinline__ void sketch_partial(const KArgs& a, const double* val
 // Reduce the G partials of this workgroup's slice of sketch rows into out[]
 // (one wave per row, fixed order).
 template <int SK>
-__device__ void reduce_partials(const KArgs& a, const long long* part, double inv, int tile, double* out)
+__device__ __forceinline__ void reduce_partials(const KArgs& a, const long long* part, double inv, int tile, double* out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r0 = (int)(((long long)tile * a.s) / a.G), r1 = (int)(((long long)(tile + 1) * a.s) / a.G);
@@ -595,6 +612,11 @@ template <typename TS, int NQ>
 __device__ __forceinline__ void forward_subst_nq(const TS* __restrict__ Pl, int k, const double* __restrict__ pv,
                                                  int nh, double* h)
 {
+    // Column-oriented: after h_c is final (lane c), every later row takes
+    // v_i -= P(i, c) h_c.  The LDS loads of the next D columns are issued
+    // before the current D steps run, so the step's critical path is
+    // readlane -> fma rather than the LDS latency.
+    constexpr int D = (NQ <= 1) ? 16 : ((NQ == 2) ? 8 : 4);   // columns in flight
     const int lane = threadIdx.x & 63;
     const int plast = (int)packed_size(k) - 1;
     double v[NQ];
@@ -603,34 +625,36 @@ __device__ __forceinline__ void forward_subst_nq(const TS* __restrict__ Pl, int 
         const int i = lane + 64 * q;
         v[q] = (i < nh) ? pv[i] : 0.0;
     }
-    // The value loaded for column c is zero wherever row i <= c or i >= nh,
-    // so the update v -= P(:, c) h_c needs no mask (fma(-0, h, v) == v) and
-    // the step's critical path is readlane -> fma.
-    double nxt[NQ];
+    // Slot d of the ring holds column c0 + d as loaded (address clamped, no
+    // condition, so the loads never become branches) and is refilled with
+    // column c0 + d + D once used.  Entries of rows i <= c or i >= nh are
+    // masked to zero at use, so the update needs no branch either
+    // (fma(-0, h, v) == v); columns c >= nh - 1 are all masked.
+    auto load = [&](int c, TS (&dst)[NQ]) {
+        const int base = packed_col(c, k) - (c + 1);     // base + i = position of P(i, c)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int i = lane + 64 * q;
-        const TS t = Pl[min(max(i - 1, 0), plast)];       // column 0: P(i, 0)
-        nxt[q] = (i > 0 && i < nh) ? (double)t : 0.0;
-    }
-    for (int c = 0; c + 1 < nh; ++c) {
-        double colv[NQ];
+        for (int q = 0; q < NQ; ++q) dst[q] = Pl[min(max(base + lane + 64 * q, 0), plast)];
+    };
+    TS ring[D][NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) colv[q] = nxt[q];
-        const int base = packed_col(c + 1, k) - (c + 2);    // base + i = position of P(i, c+1)
+    for (int d = 0; d < D; ++d) load(d, ring[d]);
+    for (int c0 = 0; c0 + 1 < nh; c0 += D) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = lane + 64 * q;
-            const TS t = Pl[min(max(base + i, 0), plast)];
-            nxt[q] = (i > c + 1 && i < nh) ? (double)t : 0.0;
+        for (int d = 0; d < D; ++d) {
+            const int c = c0 + d;
+            double src = v[0];
+#pragma unroll
+            for (int q = 1; q < NQ; ++q)
+                if ((c >> 6) == q) src = v[q];
+            const double hc = readlane_d(src, c & 63);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = lane + 64 * q;
+                const double pc = (i > c && i < nh) ? (double)ring[d][q] : 0.0;
+                v[q] = fma(-pc, hc, v[q]);
+            }
+            load(c + D, ring[d]);
         }
-        double src = v[0];
-#pragma unroll
-        for (int q = 1; q < NQ; ++q)
-            if ((c >> 6) == q) src = v[q];
-        const double hc = readlane_d(src, c & 63);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) v[q] = fma(-colv[q], hc, v[q]);
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -660,7 +684,7 @@ __device__ __forceinline__ void lds_append_row(TS* Pl, int k, const TS* __restri
 
 // Bulk-load rows 1..nh-1 of the global pivot block into the packed LDS layout.
 template <typename TS>
-__device__ void lds_load_block(TS* Pl, int k, const TS* __restrict__ P, int kp1, int nh)
+__device__ __forceinline__ void lds_load_block(TS* Pl, int k, const TS* __restrict__ P, int kp1, int nh)
 {
     const int tot = nh * (nh - 1) / 2;
     for (int e = threadIdx.x; e < tot; e += NT) {
@@ -718,7 +742,7 @@ __device__ __forceinline__ void eliminate(double (&acc)[EPT], const int (&gi)[EP
 // Per-tile argmax |v| (ties: smallest index) -> amv[slot], ami[slot];
 // a non-finite value marks the slot with index -2.
 template <int EPT>
-__device__ void tile_argmax(const double (&acc)[EPT], const int (&gi)[EPT], unsigned vmask,
+__device__ __forceinline__ void tile_argmax(const double (&acc)[EPT], const int (&gi)[EPT], unsigned vmask,
                             double* amv, int* ami, int slot)
 {
     __shared__ double s_b[NWAVE], s_v[NWAVE];
