@@ -97,18 +97,59 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// DPP move of a 64-bit value (two 32-bit moves); lanes the control does not
+// write get 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ long long dpp64(long long v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROW_MASK, 0xF, false);
+    return ((long long)hi << 32) | (unsigned int)lo;
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    return __longlong_as_double(dpp64<CTRL, ROW_MASK>(__double_as_longlong(v)));
+}
+
+// Sum over the wave left in lane 63 (other lanes hold partial sums).
+__device__ __forceinline__ double wave_sum_to63(double v)
+{
+    v += dpp_d<0xB1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);          // quad_perm [2,3,0,1]
+    v += dpp_d<0x124>(v);         // row_ror:4
+    v += dpp_d<0x128>(v);         // row_ror:8
+    v += dpp_d<0x142, 0xA>(v);    // row_bcast:15 into rows 1, 3
+    v += dpp_d<0x143, 0xC>(v);    // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// Sum over the wave, returned to every lane.  DPP steps: quad xor 1 and 2,
+// rotations by 4 and 8 inside each row of 16, then row 0 -> 1, 2 -> 3 and
+// lane 31 -> rows 2, 3; lane 63 ends with the total.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_d<0xB1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);          // quad_perm [2,3,0,1]
+    v += dpp_d<0x124>(v);         // row_ror:4
+    v += dpp_d<0x128>(v);         // row_ror:8
+    v += dpp_d<0x142, 0xA>(v);    // row_bcast:15 into rows 1, 3
+    v += dpp_d<0x143, 0xC>(v);    // row_bcast:31 into rows 2, 3
+    return readlane_d(v, 63);
 }
 
 __device__ __forceinline__ long long wave_sum_ll(long long v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp64<0xB1>(v);
+    v += dpp64<0x4E>(v);
+    v += dpp64<0x124>(v);
+    v += dpp64<0x128>(v);
+    v += dpp64<0x142, 0xA>(v);
+    v += dpp64<0x143, 0xC>(v);
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
+    return ((long long)hi << 32) | (unsigned int)lo;
 }
 
 // (|v|, index) ordering: larger magnitude wins, ties go to the smaller index.

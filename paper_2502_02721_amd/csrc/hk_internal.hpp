@@ -120,11 +120,14 @@ __host__ __device__ inline long long packed_size(int k) { return (long long)k * 
 
 struct LsArgs {
     int s, k;
+    int nb;                      // panel width of the blocked kernel (0: column-by-column kernel)
     double lam;
     const double* Z; const double* F; const double* c;
     double* Q; double* R; double* r; double* y; double* res; double* d;
     Ctl* ctl;
+    unsigned long long* trace;   // LS_TRACE timestamps, or null
 };
+constexpr int LS_TRACE = 256;    // timestamp slots of the least-squares kernel
 
 struct CombineArgs {
     int n, k;
@@ -157,5 +160,7 @@ hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double*
                               int ncols, void* dst, hipStream_t st);
 hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int lds_bytes, int* blocks_per_cu);
 size_t small_ls_lds_bytes(int s, int k, double lam);
+int small_ls_panel(int s, int k, double lam, size_t lds_max);
+hipError_t launch_small_ls_blocked(int nb, const LsArgs& a, hipStream_t st);
 
 }  // namespace hk

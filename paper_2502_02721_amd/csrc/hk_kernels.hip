@@ -229,6 +229,7 @@ size_t small_ls_lds_bytes(int s, int k, double lam)
 
 hipError_t launch_small_ls(const LsArgs& a, hipStream_t st)
 {
+    if (a.nb > 0) return launch_small_ls_blocked(a.nb, a, st);
     const size_t lds = small_ls_lds_bytes(a.s, a.k, a.lam);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)small_ls_kernel,
