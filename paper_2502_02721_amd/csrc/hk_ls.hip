@@ -1,6 +1,6 @@
 // Small sketched least-squares solve in one workgroup, blocked:
 //   min_y ||c - Z y||^2 + lam^2 ||F y||^2   (lambda-squared weighting, the
-//   objective of the sketched Tikhonov problem of Section 3.2), i.e. the QR
+//   objective of the sketched Tikhonov problem of Sec. 3.3), i.e. the QR
 //   factorisation of M = [Z; lam F] (R rows) with the right-hand side
 //   [c; 0] appended as column kd.
 //

@@ -5,8 +5,8 @@ oracle alone.
 The oracle is solved on b and on copies of b with random one-ulp
 perturbations.  The spread between those FP64 solves is how much of the
 result the FP64 arithmetic itself does not determine for this workload: the
-generalized Hessenberg process with partial pivoting (Section 3.1,
-Algorithm 2) is stable in practice but not backward stable, and on this
+generalized Hessenberg process with partial pivoting (Sec. 3.1; the sLSLU
+iteration of Algorithm 1) is stable in practice but not backward stable, and on this
 operator small differences in the basis grow from step to step.  Recorded per
 perturbation: the first step where the pivot sequences t / g differ, the
 near-tie gap 1 - |d(t')| (resp. |l(g')|) of the unperturbed vector at the
