@@ -4,24 +4,38 @@
 //   factorisation of M = [Z; lam F] (R rows) with the right-hand side
 //   [c; 0] appended as column kd.
 //
-// Block classical Gram-Schmidt with reorthogonalisation (BCGS2): panels of NB
+// Block classical Gram-Schmidt with reorthogonalisation (BCGS2): panels of 16
 // columns are held in LDS; each panel is projected twice against the Q
-// columns already built (kept in global memory), then orthonormalised column
-// by column with CGS2 inside the panel.  The appended column ends as
-// (d, rho) with d = Q^T [c; 0] and rho the norm of the part of [c; 0] outside
-// range(M), so the minimised objective with the first j columns is
-// res[j-1] = sqrt(sum_{i >= j} d_i^2 + rho^2), and y = R^{-1} d.
+// columns already built (kept in global memory) with FP64 MFMA products
+// (W = Q^T P, P -= Q W), then factored inside the panel by CholeskyQR2 on the
+// column-scaled panel, which is exact to rounding whenever the panel is well
+// conditioned; a panel whose scaled Gram matrix has a pivot below 1e-12 (a
+// condition number above about 1e6) is factored by column-by-column CGS2
+// instead.  The appended column ends as (d, rho) with d = Q^T [c; 0] and rho
+// the norm of the part of [c; 0] outside range(M), so the minimised objective
+// with the first j columns is res[j-1] = sqrt(sum_{i >= j} d_i^2 + rho^2),
+// and y = R^{-1} d.
 #include "hk_device.hpp"
 
 namespace hk {
 
 constexpr int LSB_NT = 512;
 constexpr int LSB_NW = LSB_NT / 64;
-constexpr int LSB_TROWS = 32;     // rows per lane in proj_tn: R <= 4 * LSB_TROWS * LSB_NW
+constexpr int PNB = 16;                            // panel width (the MFMA tile)
+constexpr double CHOL_TINY = 1e-12;                // smallest accepted scaled pivot
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 operand layout: lane l holds A(l % 16, l / 16) and
+// B(l / 16, l % 16); element v of the accumulator is D(l / 16 + 4 v, l % 16)
+// (checked on gfx950).
+__device__ __forceinline__ d4v mfma16(double a, double b, d4v d)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+}
 
 // Sum over the workgroup of NV values per thread; the totals land in out[]
-// (LDS) for every thread to read.  red holds LSB_NW * NV doubles.  The NV
-// wave sums are independent DPP chains, so they overlap.
+// (LDS) for every thread to read.  red holds LSB_NW * NV doubles.
 template <int NV>
 __device__ __forceinline__ void block_multi_sum(double (&v)[NV], double* red, double* out)
 {
@@ -55,92 +69,213 @@ __device__ __forceinline__ double block_sum1(double v, double* red)
     return t;
 }
 
-// W[c * NB + p] = sum_i Q[c * R + i] P[p * R + i] for c < j0, p < NB.
-// Blocks of 16 Q columns; wave w takes a slice of the rows; lane (cc, ro)
-// handles column cc of the block and rows ro, ro + 4, ... of the slice.
-template <int NB>
+// W[c * 16 + p] = sum_i Q[c * R + i] P[p * R + i] for c < j0 (MFMA: A = Q^T
+// block, B = P block, K = rows).  Work units: ncb column blocks x nsplit row
+// groups (at most 8 units at a time, one per wave); row-group partials are
+// summed through red (at most 8 x 256 doubles).
 __device__ void proj_tn(const double* __restrict__ Q, int R, int j0, const double* P, double* W, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int cc = lane & 15, ro = lane >> 4;
-    const int slice = (((R + LSB_NW - 1) / LSB_NW) + 3) & ~3;   // <= 4 * LSB_TROWS
-    const int r0 = wave * slice, r1 = min(R, r0 + slice);
-    const int nt = (max(r1 - r0, 0) + 3) >> 2;                   // rows per lane
-    for (int cb = 0; cb < j0; cb += 16) {
-        const int c = cb + cc;
+    const int ncb = (j0 + 15) >> 4;
+    const int nsplit = max(1, LSB_NW / ncb);
+    const int rows_per = (((R + nsplit - 1) / nsplit) + 3) & ~3;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int u0 = 0; u0 < ncb * nsplit; u0 += LSB_NW) {
+        const int u = u0 + wave;
+        const bool active = u < ncb * nsplit;
+        const int cb = active ? u / nsplit : 0, g = active ? u - cb * nsplit : 0;
+        const int c = cb * 16 + li;
+        const bool cok = active && c < j0;
         const double* qc = Q + (long long)min(c, j0 - 1) * R;
-        double acc[NB];
+        const double* pc = P + li * R;
+        const int r0 = g * rows_per, r1 = active ? min(R, r0 + rows_per) : r0;
+        d4v d = {0.0, 0.0, 0.0, 0.0};
+        int i0 = r0;
+        for (; i0 + 16 <= r1; i0 += 16) {          // four K steps in flight
+            double qa[4], pb[4];
 #pragma unroll
-        for (int p = 0; p < NB; ++p) acc[p] = 0.0;
-        // the lane's rows in chunks of 16 Q values in flight (clamped
-        // addresses; rows past the slice are masked at use)
-        for (int t0 = 0; t0 < nt; t0 += 16) {
-            double q[16];
+            for (int t = 0; t < 4; ++t) {
+                const int row = i0 + 4 * t + lk;
+                qa[t] = qc[row];
+                pb[t] = pc[row];
+            }
 #pragma unroll
-            for (int t = 0; t < 16; ++t) q[t] = qc[min(r0 + ro + 4 * (t0 + t), R - 1)];
+            for (int t = 0; t < 4; ++t) d = mfma16(cok ? qa[t] : 0.0, pb[t], d);
+        }
+        for (; i0 < r1; i0 += 4) {
+            const int row = i0 + lk;
+            const bool rok = row < r1;
+            const double qa = qc[min(row, R - 1)];
+            const double pb = pc[min(row, R - 1)];
+            d = mfma16((cok && rok) ? qa : 0.0, rok ? pb : 0.0, d);
+        }
+        if (nsplit == 1) {
+            if (active) {
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                if (t0 + t < nt) {
-                    const int row = r0 + ro + 4 * (t0 + t);
-                    const int i = min(row, R - 1);
-                    const double qt = (row < r1 && c < j0) ? q[t] : 0.0;
-#pragma unroll
-                    for (int p = 0; p < NB; ++p) acc[p] = fma(qt, P[p * R + i], acc[p]);
+                for (int v = 0; v < 4; ++v) {
+                    const int cr = cb * 16 + lk + 4 * v;
+                    if (cr < j0) W[cr * PNB + li] = d[v];
                 }
             }
-        }
-        // sum over the 4 row offsets (lanes cc, cc+16, cc+32, cc+48)
+        } else {
 #pragma unroll
-        for (int p = 0; p < NB; ++p) {
-            acc[p] += __shfl_xor(acc[p], 16);
-            acc[p] += __shfl_xor(acc[p], 32);
+            for (int v = 0; v < 4; ++v) red[wave * 256 + (lk + 4 * v) * 16 + li] = active ? d[v] : 0.0;
         }
-        if (ro == 0) {
-#pragma unroll
-            for (int p = 0; p < NB; ++p) red[(wave * 16 + cc) * NB + p] = acc[p];
-        }
+    }
+    if (nsplit > 1) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 16 * NB; e += LSB_NT) {
-            const int c2 = cb + e / NB;
+        // ncb * nsplit <= LSB_NW here: unit u = cb * nsplit + g sits in red[u]
+        for (int e = threadIdx.x; e < ncb * 256; e += LSB_NT) {
+            const int cb = e >> 8, ij = e & 255;
+            const int cr = cb * 16 + (ij >> 4);
             double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < LSB_NW; ++w) t += red[w * 16 * NB + e];
-            if (c2 < j0) W[c2 * NB + (e % NB)] = t;
+            for (int g = 0; g < nsplit; ++g) t += red[(cb * nsplit + g) * 256 + ij];
+            if (cr < j0) W[cr * PNB + (ij & 15)] = t;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+}
+
+// P[p * R + i] -= sum_{c < j0} Q[c * R + i] W[c * 16 + p] (MFMA: D = P block of
+// 16 rows, A = Q block, B = W block, K = Q columns).
+__device__ void proj_update(const double* __restrict__ Q, int R, int j0, double* P, const double* W)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nrb = (R + 15) >> 4;
+    for (int rb = wave; rb < nrb; rb += LSB_NW) {
+        const int rA = rb * 16 + li;               // row of the A operand
+        const bool rAok = rA < R;
+        const double* qrow = Q + min(rA, R - 1);
+        d4v d;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = rb * 16 + lk + 4 * v;
+            d[v] = row < R ? P[li * R + row] : 0.0;
+        }
+        int c = 0;
+        for (; c + 16 <= j0; c += 16) {            // four K steps in flight
+            double qa[4], wb[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int cc = c + 4 * t + lk;
+                qa[t] = qrow[(long long)cc * R];
+                wb[t] = W[cc * PNB + li];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) d = mfma16(rAok ? -qa[t] : 0.0, wb[t], d);
+        }
+        for (; c < j0; c += 4) {
+            const int cc = c + lk;
+            const bool ok = cc < j0;
+            const double qa = qrow[(long long)min(cc, j0 - 1) * R];
+            const double wb = W[min(cc, j0 - 1) * PNB + li];
+            d = mfma16((ok && rAok) ? -qa : 0.0, ok ? wb : 0.0, d);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = rb * 16 + lk + 4 * v;
+            if (row < R) P[li * R + row] = d[v];
+        }
     }
 }
 
-// P[p * R + i] -= sum_{c < j0} Q[c * R + i] W[c * NB + p]; one row per
-// thread, columns in increasing order.
-template <int NB>
-__device__ void proj_update(const double* __restrict__ Q, int R, int j0, double* P, const double* W)
+// G = P^T P (16 x 16, LDS), rows split over the waves (MFMA with A = P^T and
+// B = P: lane l holds the same element P(row, l % 16) for both).
+__device__ void panel_gram(const double* P, int R, double* G, double* red)
 {
-    constexpr int U = 16;                          // Q values in flight per thread
-    for (int i = threadIdx.x; i < R; i += LSB_NT) {
-        double v[NB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int slice = (((R + LSB_NW - 1) / LSB_NW) + 3) & ~3;
+    const int r0 = wave * slice, r1 = min(R, r0 + slice);
+    const double* pc = P + li * R;
+    d4v d = {0.0, 0.0, 0.0, 0.0};
+    for (int i0 = r0; i0 < r1; i0 += 4) {
+        const int row = i0 + lk;
+        const double x = row < r1 ? pc[row] : 0.0;
+        d = mfma16(x, x, d);
+    }
 #pragma unroll
-        for (int p = 0; p < NB; ++p) v[p] = P[p * R + i];
-        for (int c = 0; c < j0; c += U) {
-            double q[U];
+    for (int v = 0; v < 4; ++v) red[wave * 256 + (lk + 4 * v) * 16 + li] = d[v];
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        double t = 0.0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) q[u] = Q[(long long)min(c + u, j0 - 1) * R + i];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (c + u < j0) {
-#pragma unroll
-                    for (int p = 0; p < NB; ++p) v[p] = fma(-q[u], W[(c + u) * NB + p], v[p]);
-                }
+        for (int w = 0; w < LSB_NW; ++w) t += red[w * 256 + threadIdx.x];
+        G[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// One CholeskyQR stage on the nb leading panel columns:
+//   G = P^T P, s = sqrt(diag G) (scale = true) or 1, S^-1 G S^-1 = L L^T,
+//   P <- P S^-1 L^-T, and the stage's factor Rs = L^T S (upper) replaces
+//   rcur by Rs rcur.  Returns false (P untouched) when a pivot of the scaled
+//   Gram matrix is below CHOL_TINY.  G, Lm, rcur, rtmp: 256 doubles each.
+__device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, double* Lm, double* sc,
+                             double* rcur, double* rtmp, double* red, int* s_ok)
+{
+    panel_gram(P, R, G, red);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        if (lane < PNB) sc[lane] = (lane < nb) ? (scale ? sqrt(G[lane * 16 + lane]) : 1.0) : 1.0;
+        __builtin_amdgcn_wave_barrier();
+        bool ok = true;
+        for (int q = lane; q < 256; q += 64) {
+            const int i = q >> 4, j = q & 15;
+            Lm[q] = (i < nb && j < nb) ? G[q] / (sc[i] * sc[j]) : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int c = 0; c < nb; ++c) {             // right-looking Cholesky, lower triangle
+            const double piv = Lm[c * 16 + c];
+            if (!(piv > CHOL_TINY) || !isfinite(piv)) { ok = false; break; }
+            const double lc = sqrt(piv);
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) Lm[c * 16 + c] = lc;
+            if (lane > c && lane < nb) Lm[lane * 16 + c] = Lm[lane * 16 + c] / lc;
+            __builtin_amdgcn_wave_barrier();
+            for (int q = lane; q < 256; q += 64) {
+                const int i = q >> 4, j = q & 15;
+                if (j > c && i >= j && i < nb) Lm[q] = fma(-Lm[i * 16 + c], Lm[j * 16 + c], Lm[q]);
             }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane == 0) *s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*s_ok) return false;
+    // rows: y L^T = x S^-1, forward over the columns
+    for (int i = threadIdx.x; i < R; i += LSB_NT) {
+        double y[PNB];
+#pragma unroll
+        for (int j = 0; j < PNB; ++j) {
+            double t = (j < nb) ? P[j * R + i] / sc[j] : 0.0;
+#pragma unroll
+            for (int q = 0; q < j; ++q) t = fma(-y[q], Lm[j * 16 + q], t);
+            y[j] = (j < nb) ? t / Lm[j * 16 + j] : 0.0;
         }
 #pragma unroll
-        for (int p = 0; p < NB; ++p) P[p * R + i] = v[p];
+        for (int j = 0; j < PNB; ++j)
+            if (j < nb) P[j * R + i] = y[j];
     }
+    // rcur <- (L^T S) rcur
+    if (threadIdx.x < 256) {
+        const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+        double t = 0.0;
+        if (i <= j && j < nb)
+            for (int q = i; q <= j; ++q) t = fma(Lm[q * 16 + i] * sc[q], rcur[q * 16 + j], t);
+        rtmp[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) rcur[threadIdx.x] = rtmp[threadIdx.x];
+    __syncthreads();
+    return true;
 }
 
 template <int NB>
 __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
 {
+    static_assert(NB == PNB, "panel width is the MFMA tile");
     extern __shared__ __align__(16) unsigned char smem[];
     // timestamps: slot 0 start, 1 end, 8 + 8 b + id for panel b
     auto mark = [&](int slot) {
@@ -156,13 +291,19 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
     const int ncol = kd + 1;                       // basis columns + right-hand side
     double* P = (double*)smem;                     // NB x R panel, column-major
     double* W = P + (size_t)NB * R;                // (k + 1) x NB projections
-    double* red = W + (size_t)(k + 1) * NB;        // LSB_NW x 16 x NB
-    double* coef = red + LSB_NW * 16 * NB;         // 16
-    double* racc = coef + 16;                      // (k + 1) x NB: R(0 .. col, col) of the panel (d for column kd)
+    double* red = W + (size_t)(k + 1) * NB;        // LSB_NW x 256
+    double* racc = red + LSB_NW * 256;             // (k + 1) x NB: R(0 .. col, col) of the panel (d for column kd)
+    double* G = racc + (size_t)(k + 1) * NB;       // 256
+    double* Lm = G + 256;                          // 256
+    double* rcur = Lm + 256;                       // 256: R of the panel's own block
+    double* rtmp = rcur + 256;                     // 256
+    double* sc = rtmp + 256;                       // 16
+    double* coef = sc + 16;                        // 16
     double* Rm = a.R;                              // k x k, column-major: Rm[col * k + row]
     double* dv = a.d;
     double* Q = a.Q;                               // R x k, column-major
     __shared__ double s_rho;
+    __shared__ int s_ok;
 
     for (int e = threadIdx.x; e < kd * k; e += LSB_NT) Rm[e] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -197,76 +338,99 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
             }
         }
         for (int e = threadIdx.x; e < (k + 1) * NB; e += LSB_NT) racc[e] = 0.0;
+        if (threadIdx.x < 256) rcur[threadIdx.x] = ((threadIdx.x >> 4) == (threadIdx.x & 15)) ? 1.0 : 0.0;
         __syncthreads();
         const int pb = 8 + 8 * (j0 / NB);
         mark(pb);
         // ---- two projections against Q(:, 0 .. j0)
         if (j0 > 0) {
             for (int pass = 0; pass < 2; ++pass) {
-                proj_tn<NB>(Q, R, j0, P, W, red);
+                proj_tn(Q, R, j0, P, W, red);
                 mark(pb + 1 + 2 * pass);
-                proj_update<NB>(Q, R, j0, P, W);
+                proj_update(Q, R, j0, P, W);
                 for (int e = threadIdx.x; e < j0 * NB; e += LSB_NT) racc[e] += W[e];
                 __syncthreads();
                 mark(pb + 2 + 2 * pass);
             }
         }
-        // ---- inside the panel: CGS2 column by column
-        for (int p = 0; p < nb; ++p) {
-            const int col = j0 + p;
-            // fine marks for the columns of panel 1: 160 + 8 p + id
-            const int fm = (j0 == NB) ? 160 + 8 * p : LS_TRACE;
-            mark(fm);
-            if (p > 0) {
-                for (int pass = 0; pass < 2; ++pass) {
-                    double part[16];
+        // ---- inside the panel: CholeskyQR2 (column-scaled first stage), or
+        // CGS2 column by column for an ill-conditioned panel
+        int stages = 0;
+        while (stages < 2 && cholqr_stage(P, R, nb, stages == 0, G, Lm, sc, rcur, rtmp, red, &s_ok)) ++stages;
+        if (stages < 2) {
+            // rtmp accumulates the CGS2 factor of the current P (upper, 16 x 16)
+            if (threadIdx.x < 256) rtmp[threadIdx.x] = 0.0;
+            __syncthreads();
+            for (int p = 0; p < nb; ++p) {
+                if (p > 0) {
+                    for (int pass = 0; pass < 2; ++pass) {
+                        double part[16];
 #pragma unroll
-                    for (int t = 0; t < 16; ++t) part[t] = 0.0;
-                    // loads are unconditional (all NB panel columns exist);
-                    // columns t >= p contribute zero
-                    for (int i = threadIdx.x; i < R; i += LSB_NT) {
-                        const double x = P[p * R + i];
+                        for (int t = 0; t < 16; ++t) part[t] = 0.0;
+                        for (int i = threadIdx.x; i < R; i += LSB_NT) {
+                            const double x = P[p * R + i];
 #pragma unroll
-                        for (int t = 0; t < NB; ++t) {
-                            const double pt = P[t * R + i];
-                            part[t] = fma(t < p ? pt : 0.0, x, part[t]);
+                            for (int t = 0; t < NB; ++t) {
+                                const double pt = P[t * R + i];
+                                part[t] = fma(t < p ? pt : 0.0, x, part[t]);
+                            }
                         }
-                    }
-                    mark(fm + 1 + 3 * pass);
-                    block_multi_sum<16>(part, red, coef);
-                    mark(fm + 2 + 3 * pass);
-                    for (int i = threadIdx.x; i < R; i += LSB_NT) {
-                        double x = P[p * R + i];
+                        block_multi_sum<16>(part, red, coef);
+                        for (int i = threadIdx.x; i < R; i += LSB_NT) {
+                            double x = P[p * R + i];
 #pragma unroll
-                        for (int t = 0; t < NB; ++t) {
-                            const double pt = P[t * R + i];
-                            x = fma(t < p ? -coef[t] : 0.0, pt, x);
+                            for (int t = 0; t < NB; ++t) {
+                                const double pt = P[t * R + i];
+                                x = fma(t < p ? -coef[t] : 0.0, pt, x);
+                            }
+                            P[p * R + i] = x;
                         }
-                        P[p * R + i] = x;
+                        if (threadIdx.x < p) rtmp[threadIdx.x * 16 + p] += coef[threadIdx.x];
+                        __syncthreads();
                     }
-                    if (threadIdx.x < p) racc[(j0 + threadIdx.x) * NB + p] += coef[threadIdx.x];
-                    __syncthreads();
-                    mark(fm + 3 + 3 * pass);
                 }
-            }
-            double nn = 0.0;
-            for (int i = threadIdx.x; i < R; i += LSB_NT) {
-                const double x = P[p * R + i];
-                nn = fma(x, x, nn);
-            }
-            const double nrm = sqrt(block_sum1(nn, red));
-            mark(fm + 7);
-            if (col < kd) {
-                if (!(nrm > 0.0) || !isfinite(nrm)) {
-                    if (threadIdx.x == 0) { a.ctl->ls_status = -4; a.ctl->status = -4; }
-                    return;
+                double nn = 0.0;
+                for (int i = threadIdx.x; i < R; i += LSB_NT) {
+                    const double x = P[p * R + i];
+                    nn = fma(x, x, nn);
                 }
-                for (int i = threadIdx.x; i < R; i += LSB_NT) P[p * R + i] = P[p * R + i] / nrm;
-                if (threadIdx.x == 0) racc[col * NB + p] = nrm;
-            } else if (threadIdx.x == 0) {
-                s_rho = nrm;
+                const double nrm = sqrt(block_sum1(nn, red));
+                if (nrm > 0.0 && isfinite(nrm))
+                    for (int i = threadIdx.x; i < R; i += LSB_NT) P[p * R + i] = P[p * R + i] / nrm;
+                if (threadIdx.x == 0) rtmp[p * 16 + p] = nrm;
+                __syncthreads();
+            }
+            // rcur <- rtmp rcur (G as scratch)
+            if (threadIdx.x < 256) {
+                const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+                double t = 0.0;
+                if (i <= j && j < nb)
+                    for (int q = i; q <= j; ++q) t = fma(rtmp[i * 16 + q], rcur[q * 16 + j], t);
+                G[threadIdx.x] = t;
             }
             __syncthreads();
+            if (threadIdx.x < 256) rcur[threadIdx.x] = G[threadIdx.x];
+            __syncthreads();
+        }
+        // the panel's own block of R; a basis column with a zero (or non-finite)
+        // diagonal makes the sketched problem rank deficient
+        if (threadIdx.x < 256) {
+            const int i = threadIdx.x >> 4, p = threadIdx.x & 15;
+            if (i <= p && p < nb) racc[(j0 + i) * NB + p] = rcur[i * 16 + p];
+        }
+        if (threadIdx.x == 0) {
+            int bad = 0;
+            for (int p = 0; p < nb; ++p) {
+                const double dg = rcur[p * 16 + p];
+                if (j0 + p < kd && (!(dg > 0.0) || !isfinite(dg))) bad = 1;
+                if (j0 + p == kd) s_rho = fabs(dg);
+            }
+            s_ok = bad ? 0 : 1;
+        }
+        __syncthreads();
+        if (!s_ok) {
+            if (threadIdx.x == 0) { a.ctl->ls_status = -4; a.ctl->status = -4; }
+            return;
         }
         mark(pb + 5);
         // ---- the panel's orthonormal columns join Q; its R columns (and d)
@@ -341,31 +505,30 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
     mark(1);
 }
 
-// LDS bytes of the blocked kernel for panel width NB
-static size_t lsb_bytes(int nb, int rows, int k)
+// LDS bytes of the blocked kernel (panel width 16)
+static size_t lsb_bytes(int rows, int k)
 {
-    return sizeof(double) * ((size_t)nb * rows + 2 * (size_t)(k + 1) * nb + (size_t)LSB_NW * 16 * nb + 16);
+    return sizeof(double) * ((size_t)PNB * rows + 2 * (size_t)(k + 1) * PNB + (size_t)LSB_NW * 256 + 4 * 256 + 32);
 }
 
 int small_ls_panel(int s, int k, double lam, size_t lds_max)
 {
     const int rows = lam > 0.0 ? 2 * s : s;
-    if (rows <= 4 * LSB_TROWS * LSB_NW && lsb_bytes(16, rows, k) + 256 <= lds_max)
-        return 16;                                 // 256: static LDS of the kernel
+    if (lsb_bytes(rows, k) + 256 <= lds_max) return PNB;   // 256: static LDS of the kernel
     return 0;
 }
 
 hipError_t launch_small_ls_blocked(int nb, const LsArgs& a, hipStream_t st)
 {
     const int rows = a.lam > 0.0 ? 2 * a.s : a.s;
-    const size_t lds = lsb_bytes(nb, rows, a.k);
-    if (nb != 16) return hipErrorInvalidValue;
+    const size_t lds = lsb_bytes(rows, a.k);
+    if (nb != PNB) return hipErrorInvalidValue;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)small_ls_blocked_kernel<16>,
+        hipError_t e = hipFuncSetAttribute((const void*)small_ls_blocked_kernel<PNB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(small_ls_blocked_kernel<16>, dim3(1), dim3(LSB_NT), lds, st, a);
+    hipLaunchKernelGGL(small_ls_blocked_kernel<PNB>, dim3(1), dim3(LSB_NT), lds, st, a);
     return hipGetLastError();
 }
 
