@@ -106,6 +106,8 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
     unsigned short* tab2 = a.lds_skt ? (unsigned short*)(smem + a.lds_skt) : nullptr;
     unsigned short* tab1 = tab2 ? tab2 + (size_t)a.spm.TY * a.spm.TX * a.zeta : nullptr;
     __shared__ int s_nw;                          // length of wlist
+    __shared__ double s_amv;                      // global argmax of the phase
+    __shared__ int s_ami;
 
     const int G = a.G;
     const int tile = tile_of_block(G, a.xcd_map);
@@ -187,27 +189,42 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
     for (int j = 0; j <= k; ++j) {
         const int par = j & 1;            // buffers written in this phase
         const int prv = par ^ 1;          // buffers written in the previous phase
-        // ---- 1. pivot p_j and eta_j = v_j(p_j)
+        // ---- 1. pivot p_j and eta_j = v_j(p_j) (wave 0), overlapped with
+        // ---- 2. the previous column's sketch rows of this workgroup's slice
+        //         (waves 1 .. NWAVE-1, one row per task)
         double eta;
         int p;
         mark(j, 0);
-        global_argmax(a.amv + prv * G, a.ami + prv * G, 0, G, eta, p);
+        {
+            const int r0 = (int)(((long long)tile * a.s) / G), r1 = (int)(((long long)(tile + 1) * a.s) / G);
+            const int nr = r1 - r0;
+            const int ntask = (j >= 1) ? nr * ((j == 1 ? 1 : 0) + 1 + (a.lam > 0.0 ? 1 : 0)) : 0;
+            const int wave = threadIdx.x >> 6;
+            if (wave == 0) {
+                global_argmax_wave(a.amv + prv * G, a.ami + prv * G, 0, G, &s_amv, &s_ami);
+            } else {
+                for (int t = wave - 1; t < ntask; t += NWAVE - 1) {
+                    const int kind = t / nr, r = r0 + (t - kind * nr);
+                    if (kind == 0) {            // z_{j-1}
+                        reduce_row<SK>(a.zpart + prv * GS, G, a.s, r, (SK == SK_SPARSE) ? inv_sk / a.scz : inv_sk,
+                                       a.Z + (long long)(j - 1) * a.s);
+                    } else if (kind == 1 && a.lam > 0.0) {   // f_{j-1}
+                        const double scf = scf_l[j - 1];
+                        reduce_row<SK>(a.fpart + prv * GS, G, a.s, r,
+                                       ((SK == SK_SPARSE) ? inv_sk / scf : inv_sk) * sc_l[j - 1],
+                                       a.F + (long long)(j - 1) * a.s);
+                    } else {                    // c = S2 b (after step 0)
+                        reduce_row<SK>(a.cpart, G, a.s, r, (SK == SK_SPARSE) ? inv_sk / scc : inv_sk, a.c);
+                    }
+                }
+            }
+            __syncthreads();
+            eta = s_amv;
+            p = s_ami;
+        }
         mark(j, 1);
         if (p == -2) { fail(-4); return; }
         const bool brk = (eta == 0.0) || (j >= a.n);
-        // ---- 2. sketches of the previous column
-        if (j == 1) reduce_partials<SK>(a, a.cpart, (SK == SK_SPARSE) ? inv_sk / scc : inv_sk, tile, a.c);
-        if (j >= 1) {
-            const double sprev = sc_l[j - 1];
-            reduce_partials<SK>(a, a.zpart + prv * GS, (SK == SK_SPARSE) ? inv_sk / a.scz : inv_sk, tile,
-                                a.Z + (long long)(j - 1) * a.s);
-            if (a.lam > 0.0) {
-                const double scf = scf_l[j - 1];
-                reduce_partials<SK>(a, a.fpart + prv * GS,
-                                    ((SK == SK_SPARSE) ? inv_sk / scf : inv_sk) * sprev, tile,
-                                    a.F + (long long)(j - 1) * a.s);
-            }
-        }
         mark(j, 2);
         if (brk) {
             if (tile == 0 && threadIdx.x == 0 && j >= 1) a.H[(long long)(j - 1) * kp1 + j] = 0.0;
@@ -242,32 +259,63 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 pm.bits[oe >> 5] |= 1u << (oe & 31);
             }
         }
-        for (int c = threadIdx.x; c < j; c += NT)            // P(j, c) = l_c(p_j)
-            Pl[packed_col(c, k) + (j - c - 1)] = (TB)(sc_l[c] * (double)V[(long long)c * ld + p]);
         if (j == 0) scc = fx_scale((double)a.m * fabs(eta) * 1.000001);
         mark(j, 3);
-        // u(p_i) for i < j from the window partials of A v_j, u(p_j) directly
+        // Everything below depends only on p_j, so the loads of the pivot-block
+        // row (P(j, c) = l_c(p_j)), of the window partials of A v_j left by the
+        // tiles in the previous phase, and of the stencil of (A v_j)(p_j) are
+        // all issued before any is consumed.
         double* pv = wred;                                   // pv[0..j]
         double* slotv = wred + kp1;                          // partials, [i * nslot + q]
         const double* wpp = a.wpart + (long long)prv * kp1 * a.nslot;
+        const TB* vj = V + (long long)j * ld;
+        double upj;
         {
-            constexpr int SB = 8;
+            constexpr int SBW = 2, SBS = 2;
             const int tot = j * a.nslot;
-            for (int q0 = 0; q0 < tot; q0 += SB * NT) {
-                double vv[SB];
+            const int py = p / nx, px = p - py * nx;
+            const int tw2 = tw * tw;
+            // (a) pivot-block row: thread c < j (j <= k < NT)
+            const TB gv = V[(long long)min((int)threadIdx.x, max(j - 1, 0)) * ld + p];
+            // (b) first batch of window partials
+            double wv[SBW];
 #pragma unroll
-                for (int u = 0; u < SB; ++u) {
-                    const int q = q0 + u * NT + (int)threadIdx.x;
-                    vv[u] = wpp[q < tot ? q : 0];
-                }
-#pragma unroll
-                for (int u = 0; u < SB; ++u) {
-                    const int q = q0 + u * NT + (int)threadIdx.x;
-                    if (q < tot) slotv[q] = vv[u];
-                }
+            for (int u = 0; u < SBW; ++u) {
+                const int q = u * NT + (int)threadIdx.x;
+                wv[u] = wpp[q < tot ? q : 0];
             }
+            // (c) first batch of stencil taps at p_j
+            TB sv[SBS];
+            double sw[SBS];
+#pragma unroll
+            for (int u = 0; u < SBS; ++u) {
+                const int o = u * NT + (int)threadIdx.x;
+                const int oc = o < tw2 ? o : 0;
+                const int aa = oc / tw, bb = oc - aa * tw;
+                const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
+                const bool in = o < tw2 && y >= 0 && x >= 0;
+                sv[u] = vj[in ? y * nx + x : 0];
+                sw[u] = in ? tyl[aa] * txl[bb] : 0.0;
+            }
+            // consume
+            if ((int)threadIdx.x < j)
+                Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TB)(sc_l[threadIdx.x] * (double)gv);
+#pragma unroll
+            for (int u = 0; u < SBW; ++u) {
+                const int q = u * NT + (int)threadIdx.x;
+                if (q < tot) slotv[q] = wv[u];
+            }
+            for (int q = SBW * NT + (int)threadIdx.x; q < tot; q += NT) slotv[q] = wpp[q];
+            double st = 0.0;
+#pragma unroll
+            for (int u = 0; u < SBS; ++u) st = fma(sw[u], (double)sv[u], st);
+            for (int o = SBS * NT + (int)threadIdx.x; o < tw2; o += NT) {
+                const int aa = o / tw, bb = o - aa * tw;
+                const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
+                if (y >= 0 && x >= 0) st = fma(tyl[aa] * txl[bb], (double)vj[y * nx + x], st);
+            }
+            upj = block_sum(st, s_red);                      // also publishes Pl and slotv
         }
-        __syncthreads();
         for (int i = threadIdx.x; i < j; i += NT) {
             const WBox bx = wbox(pivs[i], ny, nx, r, TY, TX);
             double sum = 0.0;
@@ -277,7 +325,6 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             pv[i] = sj * sum;
         }
         mark(j, 4);
-        const double upj = stencil_at<TB>(V + (long long)j * ld, p, ny, nx, r, a.bc, tyl, txl, s_red);
         mark(j, 5);
         if (threadIdx.x == 0) pv[j] = sj * upj;
         __syncthreads();
@@ -342,34 +389,61 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         }
         __syncthreads();
         mark(j, 10);
-        // window sums of A v_{j+1} at the pivots p_0..p_j over this tile's pixels
+        // window sums of A v_{j+1} at the pivots p_0..p_j over this tile's
+        // pixels, one wave per pivot.  A window that stays inside the image
+        // (or any window under the zero boundary) meets the tile in a
+        // rectangle: lanes take its columns (two half-waves split the rows)
+        // and the separable weights are applied per column; a window folded
+        // by the reflective boundary walks all its offsets.
         {
             const int nw = s_nw;
-            for (int q = 0; q < nw; ++q) {
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            double* wpc = a.wpart + (long long)par * kp1 * a.nslot;
+            for (int q = wave; q < nw; q += NWAVE) {
                 const int i = wlist[q];
-                const int py = pivs[i] / nx, px = pivs[i] - (pivs[i] / nx) * nx;
+                const int p = pivs[i];
+                const int py = p / nx, px = p - py * nx;
                 double acc2 = 0.0;
-                for (int o = threadIdx.x; o < tw * tw; o += NT) {
-                    const int aa = o / tw, bb = o - aa * tw;
-                    const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
-                    if (y < tm.y0 || y >= tm.y0 + TY || x < tm.x0 || x >= tm.x0 + TX || y < 0 || x < 0) continue;
-                    acc2 = fma(tyl[aa] * txl[bb], wt[(y - tm.y0) * TX + (x - tm.x0)], acc2);
+                const bool rect = a.bc == 0 || (py - r >= 0 && py + r < ny && px - r >= 0 && px + r < nx);
+                if (rect) {
+                    const int ya = max(max(py - r, tm.y0), 0), yb = min(min(py + r, tm.y0 + TY - 1), ny - 1);
+                    const int xa = max(max(px - r, tm.x0), 0), xb = min(min(px + r, tm.x0 + TX - 1), nx - 1);
+                    const int x = xa + (lane & 31);
+                    if (x <= xb) {
+                        double cs = 0.0;
+                        for (int y = ya + (lane >> 5); y <= yb; y += 2)
+                            cs = fma(tyl[y - py + r], wt[(y - tm.y0) * TX + (x - tm.x0)], cs);
+                        acc2 = txl[x - px + r] * cs;
+                    }
+                } else {
+                    // reflection folds each axis separately: lanes take the
+                    // window's column offsets, half-waves split its rows
+                    for (int bb = lane & 31; bb < tw; bb += 32) {
+                        const int x = bc_map(px + bb - r, nx, a.bc);
+                        if (x < tm.x0 || x >= tm.x0 + TX) continue;
+                        double cs = 0.0;
+                        for (int aa = lane >> 5; aa < tw; aa += 2) {
+                            const int y = bc_map(py + aa - r, ny, a.bc);
+                            if (y >= tm.y0 && y < tm.y0 + TY)
+                                cs = fma(tyl[aa], wt[(y - tm.y0) * TX + (x - tm.x0)], cs);
+                        }
+                        acc2 = fma(txl[bb], cs, acc2);
+                    }
                 }
                 acc2 = wave_sum(acc2);
-                if ((threadIdx.x & 63) == 0) wred[q * NWAVE + (threadIdx.x >> 6)] = acc2;
-            }
-            __syncthreads();
-            double* wpc = a.wpart + (long long)par * kp1 * a.nslot;
-            for (int q = threadIdx.x; q < nw; q += NT) {
-                double sum = 0.0;
-                for (int w = 0; w < NWAVE; ++w) sum += wred[q * NWAVE + w];
-                const int i = wlist[q];
-                const WBox bx = wbox(pivs[i], ny, nx, r, TY, TX);
-                wpc[(long long)i * a.nslot + (tyi - bx.tyl) * a.spx + (txi - bx.txl)] = sum;
+                if (lane == 0) {
+                    const WBox bx = wbox(p, ny, nx, r, TY, TX);
+                    wpc[(long long)i * a.nslot + (tyi - bx.tyl) * a.spx + (txi - bx.txl)] = acc2;
+                }
             }
         }
         mark(j, 11);
+        // sampled arrival / release times of every workgroup (tracing only)
+        unsigned long long* arr = (a.trace && (j & 7) == 4 && (j >> 3) < ARR_SAMPLES)
+                                      ? a.trace + a.trace_cap + (long long)(j >> 3) * 2 * MAXG : nullptr;
+        if (arr && threadIdx.x == 0) arr[tile] = wall_clock64();
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+        if (arr && threadIdx.x == 0) arr[MAXG + tile] = wall_clock64();
     }
 }
 

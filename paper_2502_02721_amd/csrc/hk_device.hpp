@@ -390,7 +390,19 @@ __device__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int b
         double s0 = (double)col[y0 * SW], s1 = (double)col[min(y0 + 1, SH - 1) * SW],
                s2 = (double)col[min(y0 + 2, SH - 1) * SW];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int b = 0; b < taps; ++b) {
+        int b = 0;
+        for (; b + 4 <= taps; b += 4) {            // four LDS loads in flight
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[u] = (double)col[min(y0 + b + u + 3, SH - 1) * SW];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double w = tyl[b + u];
+                a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, t[u], a3);
+                s0 = s1; s1 = s2; s2 = t[u];
+            }
+        }
+        for (; b < taps; ++b) {
             const double s3 = (double)col[min(y0 + b + 3, SH - 1) * SW];
             const double w = tyl[b];
             a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, s3, a3);
@@ -605,41 +617,50 @@ __device__ __forceinline__ void sketch_partial(const KArgs& a, const double* val
 
 // Reduce the G partials of this workgroup's slice of sketch rows into out[]
 // (one wave per row, fixed order).
+// Row r of the sketch: out[r] = inv * sum over the G workgroup partials, by
+// one wave in a fixed order.
+template <int SK>
+__device__ __forceinline__ void reduce_row(const long long* part, int G, int s, int r, double inv, double* out)
+{
+    const int lane = threadIdx.x & 63;
+    if constexpr (SK == SK_SPARSE) {
+        long long v[MAXG / 64];
+#pragma unroll
+        for (int u = 0; u < MAXG / 64; ++u) {
+            const int q = lane + 64 * u;
+            v[u] = part[(long long)(q < G ? q : 0) * s + r];
+        }
+        long long acc = 0;
+#pragma unroll
+        for (int u = 0; u < MAXG / 64; ++u)
+            if (lane + 64 * u < G) acc += v[u];
+        acc = wave_sum_ll(acc);
+        if (lane == 0) out[r] = (double)acc * inv;
+    } else {
+        const double* pd = (const double*)part;
+        double v[MAXG / 64];
+#pragma unroll
+        for (int u = 0; u < MAXG / 64; ++u) {
+            const int q = lane + 64 * u;
+            v[u] = pd[(long long)(q < G ? q : 0) * s + r];
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < MAXG / 64; ++u)
+            if (lane + 64 * u < G) acc += v[u];
+        acc = wave_sum(acc);
+        if (lane == 0) out[r] = acc * inv;
+    }
+}
+
+// Reduce the G partials of this workgroup's slice of sketch rows into out[]
+// (one wave per row, fixed order).
 template <int SK>
 __device__ __forceinline__ void reduce_partials(const KArgs& a, const long long* part, double inv, int tile, double* out)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
     const int r0 = (int)(((long long)tile * a.s) / a.G), r1 = (int)(((long long)(tile + 1) * a.s) / a.G);
-    for (int r = r0 + wave; r < r1; r += NWAVE) {
-        if constexpr (SK == SK_SPARSE) {
-            long long v[MAXG / 64];
-#pragma unroll
-            for (int u = 0; u < MAXG / 64; ++u) {
-                const int q = lane + 64 * u;
-                v[u] = part[(long long)(q < a.G ? q : 0) * a.s + r];
-            }
-            long long acc = 0;
-#pragma unroll
-            for (int u = 0; u < MAXG / 64; ++u)
-                if (lane + 64 * u < a.G) acc += v[u];
-            acc = wave_sum_ll(acc);
-            if (lane == 0) out[r] = (double)acc * inv;
-        } else {
-            const double* pd = (const double*)part;
-            double v[MAXG / 64];
-#pragma unroll
-            for (int u = 0; u < MAXG / 64; ++u) {
-                const int q = lane + 64 * u;
-                v[u] = pd[(long long)(q < a.G ? q : 0) * a.s + r];
-            }
-            double acc = 0.0;
-#pragma unroll
-            for (int u = 0; u < MAXG / 64; ++u)
-                if (lane + 64 * u < a.G) acc += v[u];
-            acc = wave_sum(acc);
-            if (lane == 0) out[r] = acc * inv;
-        }
-    }
+    for (int r = r0 + wave; r < r1; r += NWAVE) reduce_row<SK>(part, a.G, a.s, r, inv, out);
 }
 
 // ------------------------------------------------------------------------
@@ -817,34 +838,40 @@ __device__ __forceinline__ void tile_argmax(const double (&acc)[EPT], const int 
 // Reduce the G tile partials at amv[off..off+G) (every workgroup does the
 // same reduction, so all agree).  Returns the signed value and the index;
 // idx = -2 flags non-finite data.
+// Global argmax over the G workgroup partials by one wave (the caller's wave
+// 0); the result goes to *sv / *si (LDS), -2 if any partial saw a NaN.
+__device__ __forceinline__ void global_argmax_wave(const double* amv, const int* ami, int off, int G,
+                                                   double* sv, int* si)
+{
+    const int lane = threadIdx.x & 63;
+    double best = -1.0, v = 0.0;
+    int bi = INT_MAX;
+    int bad = 0;
+    int iv[MAXG / 64];
+    double vv[MAXG / 64];
+#pragma unroll
+    for (int u = 0; u < MAXG / 64; ++u) {
+        const int q = lane + 64 * u;
+        const int qq = off + (q < G ? q : 0);
+        iv[u] = ami[qq];
+        vv[u] = amv[qq];
+    }
+#pragma unroll
+    for (int u = 0; u < MAXG / 64; ++u) {
+        if (lane + 64 * u >= G) continue;
+        if (iv[u] == -2) bad = 1;
+        if (am_better(fabs(vv[u]), iv[u], best, bi)) { best = fabs(vv[u]); bi = iv[u]; v = vv[u]; }
+    }
+    wave_argmax(best, bi, v);
+    for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o);
+    if (lane == 0) { *sv = v; *si = bad ? -2 : bi; }
+}
+
 __device__ void global_argmax(const double* amv, const int* ami, int off, int G, double& val, int& idx)
 {
     __shared__ double s_val;
     __shared__ int s_idx;
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        double best = -1.0, v = 0.0;
-        int bi = INT_MAX;
-        int bad = 0;
-        int iv[MAXG / 64];
-        double vv[MAXG / 64];
-#pragma unroll
-        for (int u = 0; u < MAXG / 64; ++u) {
-            const int q = lane + 64 * u;
-            const int qq = off + (q < G ? q : 0);
-            iv[u] = ami[qq];
-            vv[u] = amv[qq];
-        }
-#pragma unroll
-        for (int u = 0; u < MAXG / 64; ++u) {
-            if (lane + 64 * u >= G) continue;
-            if (iv[u] == -2) bad = 1;
-            if (am_better(fabs(vv[u]), iv[u], best, bi)) { best = fabs(vv[u]); bi = iv[u]; v = vv[u]; }
-        }
-        wave_argmax(best, bi, v);
-        for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o);
-        if (lane == 0) { s_val = v; s_idx = bad ? -2 : bi; }
-    }
+    if (threadIdx.x < 64) global_argmax_wave(amv, ami, off, G, &s_val, &s_idx);
     __syncthreads();
     val = s_val;
     idx = s_idx;

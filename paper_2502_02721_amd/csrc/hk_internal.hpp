@@ -128,6 +128,11 @@ struct LsArgs {
     unsigned long long* trace;   // LS_TRACE timestamps, or null
 };
 constexpr int LS_TRACE = 256;    // timestamp slots of the least-squares kernel
+// per-workgroup barrier arrival / release timestamps of the blur kernel at
+// steps j = 8 q + 4 (q < ARR_SAMPLES): ARR_SAMPLES x 2 x MAXG slots after the
+// basis kernel's own trace
+constexpr int ARR_SAMPLES = 32;
+constexpr int ARR_SLOTS = ARR_SAMPLES * 2 * MAXG;
 
 struct CombineArgs {
     int n, k;

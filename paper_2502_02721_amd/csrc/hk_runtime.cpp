@@ -365,7 +365,7 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
     w.res = take(sizeof(double) * k);
     w.d = take(sizeof(double) * k);
     w.trace_cap = (p->flags & HK_FLAG_TRACE) ? 2 * (6 * kp1 + 8) + 16 * (kp1 + 1) : 0;
-    w.trace = take(sizeof(unsigned long long) * (size_t)std::max(1, w.trace_cap + (w.trace_cap ? LS_TRACE : 0)));
+    w.trace = take(sizeof(unsigned long long) * (size_t)std::max(1, w.trace_cap + (w.trace_cap ? ARR_SLOTS + LS_TRACE : 0)));
     w.scale = take(sizeof(double) * kp1);
     w.wpart = take(sizeof(double) * 2 * (size_t)kp1 * std::max(1, nslot));
     w.total = off;
@@ -748,7 +748,7 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
     l.res = (double*)(base + w.res);
     l.d = (double*)(base + w.d);
     l.ctl = a.ctl;
-    l.trace = w.trace_cap ? a.trace + w.trace_cap : nullptr;
+    l.trace = w.trace_cap ? a.trace + w.trace_cap + ARR_SLOTS : nullptr;
     CombineArgs& c = sv->ca;
     c.n = (int)op->n; c.k = p->k; c.L = a.L; c.ldl = a.ldl; c.y = l.y; c.ctl = a.ctl;
     c.scale = (pl.kernel == OP_BLUR_ONEBAR) ? a.scale : nullptr;
@@ -941,8 +941,9 @@ hk_status hk_solve_get_trace(hk_solve* sv, int32_t max, uint64_t* ticks, int32_t
     if (!sv->ka.trace) return fail(HK_EINVAL, "the solve was created without HK_FLAG_TRACE");
     Ctl ctl;
     HIP_TRY(hipMemcpy(&ctl, sv->ka.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-    // barrier pairs, then sub-step marks (blur kernel), then the LS kernel's marks
-    const int rec = sv->ka.trace_cap + LS_TRACE;
+    // barrier pairs, then sub-step marks (blur kernel), per-workgroup arrivals,
+    // then the LS kernel's marks
+    const int rec = sv->ka.trace_cap + ARR_SLOTS + LS_TRACE;
     const int cnt = std::min(rec, (int)max);
     if (cnt > 0) HIP_TRY(hipMemcpy(ticks, sv->ka.trace, sizeof(uint64_t) * cnt, hipMemcpyDeviceToHost));
     *n = cnt;
