@@ -102,9 +102,16 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
     double* wred = (double*)(smem + a.lds_wred);
     int* pivs = (int*)(smem + a.lds_pl_n);       // all pivots found so far
     int* wlist = (int*)(smem + a.lds_pc_n);      // pivots whose window meets this tile
-    // sparse-sign tables of S2 and S1 for this tile's elements (if they fit)
-    unsigned short* tab2 = a.lds_skt ? (unsigned short*)(smem + a.lds_skt) : nullptr;
-    unsigned short* tab1 = tab2 ? tab2 + (size_t)a.spm.TY * a.spm.TX * a.zeta : nullptr;
+    // sparse-sign row lists of S2 and S1 over this tile's elements
+    SkRows rows2{}, rows1{};
+    if constexpr (SK == SK_SPARSE) {
+        const size_t ne = (size_t)a.spm.TY * a.spm.TX * a.zeta;
+        unsigned* ob = (unsigned*)(smem + a.lds_skt);
+        rows2.offs = ob;
+        rows1.offs = ob + (a.s + 1);
+        rows2.ents = (unsigned short*)(ob + 2 * (a.s + 1));
+        rows1.ents = rows2.ents + ne;
+    }
     __shared__ int s_nw;                          // length of wlist
     __shared__ double s_amv;                      // global argmax of the phase
     __shared__ int s_ami;
@@ -131,10 +138,8 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
     const double* tyl = taps;
     const double* txl = taps + tw;
     if constexpr (SK == SK_SPARSE) {
-        if (tab2) {
-            sketch_sparse_table(a.spm, tm, a.s, a.zeta, 2u, a.seed_lo, a.seed_hi, tab2);
-            if (a.lam > 0.0) sketch_sparse_table(a.spm, tm, a.s, a.zeta, 1u, a.seed_lo, a.seed_hi, tab1);
-        }
+        sketch_rows_build(a.spm, tm, a.s, a.zeta, 2u, a.seed_lo, a.seed_hi, rows2, (unsigned*)sk);
+        if (a.lam > 0.0) sketch_rows_build(a.spm, tm, a.s, a.zeta, 1u, a.seed_lo, a.seed_hi, rows1, (unsigned*)sk);
     }
 
     int gm[EPT];
@@ -205,16 +210,14 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             } else {
                 for (int t = wave - 1; t < ntask; t += NWAVE - 1) {
                     const int kind = t / nr, r = r0 + (t - kind * nr);
+                    // partials are FP64 for both sketch kinds in this kernel
                     if (kind == 0) {            // z_{j-1}
-                        reduce_row<SK>(a.zpart + prv * GS, G, a.s, r, (SK == SK_SPARSE) ? inv_sk / a.scz : inv_sk,
-                                       a.Z + (long long)(j - 1) * a.s);
+                        reduce_row<SK_GAUSS>(a.zpart + prv * GS, G, a.s, r, inv_sk, a.Z + (long long)(j - 1) * a.s);
                     } else if (kind == 1 && a.lam > 0.0) {   // f_{j-1}
-                        const double scf = scf_l[j - 1];
-                        reduce_row<SK>(a.fpart + prv * GS, G, a.s, r,
-                                       ((SK == SK_SPARSE) ? inv_sk / scf : inv_sk) * sc_l[j - 1],
-                                       a.F + (long long)(j - 1) * a.s);
+                        reduce_row<SK_GAUSS>(a.fpart + prv * GS, G, a.s, r, inv_sk * sc_l[j - 1],
+                                             a.F + (long long)(j - 1) * a.s);
                     } else {                    // c = S2 b (after step 0)
-                        reduce_row<SK>(a.cpart, G, a.s, r, (SK == SK_SPARSE) ? inv_sk / scc : inv_sk, a.c);
+                        reduce_row<SK_GAUSS>(a.cpart, G, a.s, r, inv_sk, a.c);
                     }
                 }
             }
@@ -346,13 +349,10 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         __syncthreads();
         auto skpart = [&](uint32_t stream, double scale, long long* part) {
             if constexpr (SK == SK_SPARSE) {
-                if (tab2) {
-                    sketch_sparse_partial_tab(wt, tm, a.s, a.zeta, stream == 2u ? tab2 : tab1, scale,
-                                              (long long*)sk, part + (long long)tile * a.s);
-                    return;
-                }
+                sketch_rows_partial(wt, stream == 2u ? rows2 : rows1, a.s, (double*)(part + (long long)tile * a.s));
+            } else {
+                sketch_partial<TB, SK>(a, wt, a.spm, tm, stream, scale, sk, part, tile);
             }
-            sketch_partial<TB, SK>(a, wt, a.spm, tm, stream, scale, sk, part, tile);
         };
         skpart(2u, a.scz, a.zpart + par * GS);   // z_j
         mark(j, 15);

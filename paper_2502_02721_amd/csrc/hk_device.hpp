@@ -390,19 +390,7 @@ __device__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int b
         double s0 = (double)col[y0 * SW], s1 = (double)col[min(y0 + 1, SH - 1) * SW],
                s2 = (double)col[min(y0 + 2, SH - 1) * SW];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int b = 0;
-        for (; b + 4 <= taps; b += 4) {            // four LDS loads in flight
-            double t[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) t[u] = (double)col[min(y0 + b + u + 3, SH - 1) * SW];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double w = tyl[b + u];
-                a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, t[u], a3);
-                s0 = s1; s1 = s2; s2 = t[u];
-            }
-        }
-        for (; b < taps; ++b) {
+        for (int b = 0; b < taps; ++b) {
             const double s3 = (double)col[min(y0 + b + 3, SH - 1) * SW];
             const double w = tyl[b];
             a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, s3, a3);
@@ -549,56 +537,111 @@ __device__ void sketch_gauss_partial(const double* vals, const Space& sp, const 
     __syncthreads();
 }
 
-constexpr unsigned short TAB_NONE = 0xFFFFu;
+// Sparse-sign rows of one tile, built once per solve.  For every sketch row
+// r, ents[offs[r] .. offs[r+1]) lists the tile elements e whose column of S
+// has a nonzero in row r, as e | (negative << 15), in increasing e.  A step's
+// partial S x over the tile is then a gather per row with no atomics, summed
+// in a fixed order.
+struct SkRows {
+    unsigned* offs;          // s + 1
+    unsigned short* ents;    // E * zeta
+};
 
-// Sparse sign from a table built once per solve: tab[e * zeta + b] holds
-// (row << 1) | negative for block b of element e's column; tab[e * zeta] is
-// TAB_NONE for tile slots outside the image.
-__device__ void sketch_sparse_partial_tab(const double* vals, const Tile& ti, int s, int zeta,
-                                          const unsigned short* tab, double scale, long long* acc,
-                                          long long* out)
+__device__ void sketch_rows_build(const Space& sp, const Tile& ti, int s, int zeta, uint32_t stream,
+                                  uint32_t k0, uint32_t k1, SkRows t, unsigned* cur)
 {
-    for (int r = threadIdx.x; r < s; r += NT) acc[r] = 0;
+    // row counts in offs[r + 1]
+    for (int r = threadIdx.x; r <= s; r += NT) t.offs[r] = 0u;
     __syncthreads();
-    for (int e = threadIdx.x; e < ti.E; e += NT) {
-        const unsigned short* te = tab + e * zeta;
-        if (te[0] == TAB_NONE) continue;
-        const long long q = __double2ll_rn(vals[e] * scale);
-        if (q == 0) continue;
-        for (int b = 0; b < zeta; ++b) {
-            const unsigned ent = te[b];
-            atomicAdd((unsigned long long*)&acc[ent >> 1], (unsigned long long)((ent & 1u) ? -q : q));
-        }
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < s; r += NT) out[r] = acc[r];
-}
-
-// Build the table for the tile's elements (rows < 2^14, so an entry never
-// equals TAB_NONE).
-__device__ void sketch_sparse_table(const Space& sp, const Tile& ti, int s, int zeta, uint32_t stream,
-                                    uint32_t k0, uint32_t k1, unsigned short* tab)
-{
-    for (int e = threadIdx.x; e < ti.E; e += NT) {
-        int gi;
-        if (!elem_global(sp, ti, e, gi)) {
-            tab[e * zeta] = TAB_NONE;
-            continue;
-        }
-        for (int b4 = 0; b4 < zeta; b4 += 4) {
-            const Words w = philox10((uint32_t)gi, (uint32_t)(b4 >> 2), stream, 1u, k0, k1);
+    auto each = [&](auto&& fn) {
+        for (int e = threadIdx.x; e < ti.E; e += NT) {
+            int gi;
+            if (!elem_global(sp, ti, e, gi)) continue;
+            for (int b4 = 0; b4 < zeta; b4 += 4) {
+                const Words w = philox10((uint32_t)gi, (uint32_t)(b4 >> 2), stream, 1u, k0, k1);
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int b = b4 + qq;
-                if (b >= zeta) break;
-                const int st = (int)((unsigned)(b * s) / (unsigned)zeta);
-                const int en = (int)((unsigned)((b + 1) * s) / (unsigned)zeta);
-                const uint32_t word = w.w[qq];
-                const int row = st + (int)(((unsigned long long)(word >> 1) * (unsigned)(en - st)) >> 31);
-                tab[e * zeta + b] = (unsigned short)((row << 1) | (int)(word & 1u));
+                for (int qq = 0; qq < 4; ++qq) {
+                    const int b = b4 + qq;
+                    if (b >= zeta) break;
+                    const int st = (int)((unsigned)(b * s) / (unsigned)zeta);
+                    const int en = (int)((unsigned)((b + 1) * s) / (unsigned)zeta);
+                    const uint32_t word = w.w[qq];
+                    const int row = st + (int)(((unsigned long long)(word >> 1) * (unsigned)(en - st)) >> 31);
+                    fn(e, row, (int)(word & 1u));
+                }
             }
         }
+    };
+    each([&](int, int row, int) { atomicAdd(&t.offs[row + 1], 1u); });
+    __syncthreads();
+    // inclusive scan of offs[1 .. s] by wave 0: lane-contiguous chunks
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int C = (s + 63) / 64;
+        const int r0 = min(s, lane * C), r1 = min(s, r0 + C);
+        unsigned loc = 0u;
+        for (int r = r0; r < r1; ++r) loc += t.offs[r + 1];
+        unsigned incl = loc;                    // inclusive scan over lanes
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned up = __shfl_up(incl, o);
+            if (lane >= o) incl += up;
+        }
+        unsigned run = incl - loc;
+        for (int r = r0; r < r1; ++r) {
+            run += t.offs[r + 1];
+            t.offs[r + 1] = run;
+        }
     }
+    __syncthreads();
+    for (int r = threadIdx.x; r < s; r += NT) cur[r] = t.offs[r];
+    __syncthreads();
+    each([&](int e, int row, int neg) {
+        const unsigned pos = atomicAdd(&cur[row], 1u);
+        t.ents[pos] = (unsigned short)(e | (neg << 15));
+    });
+    __syncthreads();
+    // the slot order above depends on timing: sort each row by element
+    for (int r = threadIdx.x; r < s; r += NT) {
+        const unsigned b = t.offs[r], en = t.offs[r + 1];
+        for (unsigned q = b + 1; q < en; ++q) {
+            const unsigned short x = t.ents[q];
+            unsigned p = q;
+            while (p > b && (t.ents[p - 1] & 0x7fffu) > (x & 0x7fffu)) {
+                t.ents[p] = t.ents[p - 1];
+                --p;
+            }
+            t.ents[p] = x;
+        }
+    }
+    __syncthreads();
+}
+
+// out[r] = sum over the row's entries of +-vals[e], in list order (FP64).
+// Ends with a workgroup barrier.
+__device__ void sketch_rows_partial(const double* vals, SkRows t, int s, double* out)
+{
+    for (int r = threadIdx.x; r < s; r += NT) {
+        const unsigned b = t.offs[r], en = t.offs[r + 1];
+        double acc = 0.0;
+        unsigned q = b;
+        for (; q + 4 <= en; q += 4) {
+            unsigned short x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = t.ents[q + u];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = vals[x[u] & 0x7fffu];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += (x[u] & 0x8000u) ? -v[u] : v[u];
+        }
+        for (; q < en; ++q) {
+            const unsigned short x = t.ents[q];
+            const double v = vals[x & 0x7fffu];
+            acc += (x & 0x8000u) ? -v : v;
+        }
+        out[r] = acc;
+    }
+    __syncthreads();                            // vals may be overwritten next
 }
 
 template <typename TS, int SK>

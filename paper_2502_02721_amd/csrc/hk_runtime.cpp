@@ -199,10 +199,13 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
     a.lds_pL = a.lds_pD;
     a.pmode = 0;
     a.lds_skt = 0;
+    if (zeta > 0) {
+        // sparse-sign row lists of S2 and S1: offsets (s + 1 each, 32 bits) and
+        // entries (16 bits per nonzero); the kernel needs them
+        const size_t tabs = sizeof(unsigned) * 2 * (size_t)(s + 1) + sizeof(unsigned short) * 2 * (size_t)TY * TX * (size_t)zeta;
+        a.lds_skt = take(tabs);
+    }
     if (off > lds_max) return 0;
-    // sparse-sign tables of S2 and S1 (16 bits per nonzero) when they fit
-    const size_t tabs = sizeof(unsigned short) * 2 * (size_t)TY * TX * (size_t)zeta;
-    if (zeta > 0 && align_up(off + tabs, 16) <= lds_max) a.lds_skt = take(tabs);
     a.lds_total = (int)off;
     return a.lds_total;
 }
@@ -626,7 +629,7 @@ static hk_status max_blocks(const hk_op* op, const hk_params* p, int rect, Plan*
 {
     // probe occupancy with the LDS of the plan at #CU blocks; shrink if needed
     const hk_context* ctx = op->ctx;
-    Plan pl = plan_solve(op, p, rect, ctx->ncu, ctx->lds_max);
+    Plan pl = plan_solve(op, p, rect, ctx->ncu, ctx->lds_max - 1024);   // 1 KB: static LDS of the kernels
     if (!pl.ok) return fail(HK_EUNSUPPORTED, "%s", pl.why.c_str());
     if ((size_t)pl.lds_total > ctx->lds_max)
         return fail(HK_EUNSUPPORTED, "LDS need %d B exceeds the device limit %zu B", pl.lds_total, ctx->lds_max);
@@ -647,7 +650,7 @@ hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* p, size_t* 
     int rect = 0;
     hk_status st = validate(op, p, &rect);
     if (st) return st;
-    Plan pl = plan_solve(op, p, rect, op->ctx->ncu, op->ctx->lds_max);
+    Plan pl = plan_solve(op, p, rect, op->ctx->ncu, op->ctx->lds_max - 1024);
     if (!pl.ok) return fail(HK_EUNSUPPORTED, "%s", pl.why.c_str());
     *bytes = ws_layout(op, p, rect, pl.G, pl.nslot).total;
     return HK_OK;
