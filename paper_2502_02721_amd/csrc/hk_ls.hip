@@ -69,11 +69,11 @@ __device__ __forceinline__ double block_sum1(double v, double* red)
     return t;
 }
 
-// W[c * 16 + p] = sum_i Q[c * R + i] P[p * R + i] for c < j0 (MFMA: A = Q^T
+// W[c * 16 + p] = sum_i Q[i * QS + c] P[p * R + i] for c < j0 (MFMA: A = Q^T
 // block, B = P block, K = rows).  Work units: ncb column blocks x nsplit row
 // groups (at most 8 units at a time, one per wave); row-group partials are
 // summed through red (at most 8 x 256 doubles).
-__device__ void proj_tn(const double* __restrict__ Q, int R, int j0, const double* P, double* W, double* red)
+__device__ void proj_tn(const double* __restrict__ Q, int QS, int R, int j0, const double* P, double* W, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ncb = (j0 + 15) >> 4;
@@ -86,7 +86,7 @@ __device__ void proj_tn(const double* __restrict__ Q, int R, int j0, const doubl
         const int cb = active ? u / nsplit : 0, g = active ? u - cb * nsplit : 0;
         const int c = cb * 16 + li;
         const bool cok = active && c < j0;
-        const double* qc = Q + (long long)min(c, j0 - 1) * R;
+        const double* qc = Q + min(c, j0 - 1);    // row-major Q: qc[row * QS]
         const double* pc = P + li * R;
         const int r0 = g * rows_per, r1 = active ? min(R, r0 + rows_per) : r0;
         d4v d = {0.0, 0.0, 0.0, 0.0};
@@ -96,7 +96,7 @@ __device__ void proj_tn(const double* __restrict__ Q, int R, int j0, const doubl
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int row = i0 + 4 * t + lk;
-                qa[t] = qc[row];
+                qa[t] = qc[(long long)row * QS];
                 pb[t] = pc[row];
             }
 #pragma unroll
@@ -105,7 +105,7 @@ __device__ void proj_tn(const double* __restrict__ Q, int R, int j0, const doubl
         for (; i0 < r1; i0 += 4) {
             const int row = i0 + lk;
             const bool rok = row < r1;
-            const double qa = qc[min(row, R - 1)];
+            const double qa = qc[(long long)min(row, R - 1) * QS];
             const double pb = pc[min(row, R - 1)];
             d = mfma16((cok && rok) ? qa : 0.0, rok ? pb : 0.0, d);
         }
@@ -136,9 +136,9 @@ __device__ void proj_tn(const double* __restrict__ Q, int R, int j0, const doubl
     __syncthreads();
 }
 
-// P[p * R + i] -= sum_{c < j0} Q[c * R + i] W[c * 16 + p] (MFMA: D = P block of
+// P[p * R + i] -= sum_{c < j0} Q[i * QS + c] W[c * 16 + p] (MFMA: D = P block of
 // 16 rows, A = Q block, B = W block, K = Q columns).
-__device__ void proj_update(const double* __restrict__ Q, int R, int j0, double* P, const double* W)
+__device__ void proj_update(const double* __restrict__ Q, int QS, int R, int j0, double* P, const double* W)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -146,7 +146,7 @@ __device__ void proj_update(const double* __restrict__ Q, int R, int j0, double*
     for (int rb = wave; rb < nrb; rb += LSB_NW) {
         const int rA = rb * 16 + li;               // row of the A operand
         const bool rAok = rA < R;
-        const double* qrow = Q + min(rA, R - 1);
+        const double* qrow = Q + (long long)min(rA, R - 1) * QS;   // row-major Q
         d4v d;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -159,7 +159,7 @@ __device__ void proj_update(const double* __restrict__ Q, int R, int j0, double*
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int cc = c + 4 * t + lk;
-                qa[t] = qrow[(long long)cc * R];
+                qa[t] = qrow[cc];
                 wb[t] = W[cc * PNB + li];
             }
 #pragma unroll
@@ -168,7 +168,7 @@ __device__ void proj_update(const double* __restrict__ Q, int R, int j0, double*
         for (; c < j0; c += 4) {
             const int cc = c + lk;
             const bool ok = cc < j0;
-            const double qa = qrow[(long long)min(cc, j0 - 1) * R];
+            const double qa = qrow[min(cc, j0 - 1)];
             const double wb = W[min(cc, j0 - 1) * PNB + li];
             d = mfma16((ok && rAok) ? -qa : 0.0, ok ? wb : 0.0, d);
         }
@@ -241,6 +241,11 @@ __device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, do
             __builtin_amdgcn_wave_barrier();
         }
         if (lane == 0) *s_ok = ok ? 1 : 0;
+        // reciprocals of the scales and of L's diagonal for the row solve
+        if (ok && lane < PNB) {
+            rtmp[lane] = (lane < nb) ? 1.0 / sc[lane] : 0.0;
+            rtmp[16 + lane] = (lane < nb) ? 1.0 / Lm[lane * 16 + lane] : 0.0;
+        }
     }
     __syncthreads();
     if (!*s_ok) return false;
@@ -249,25 +254,25 @@ __device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, do
         double y[PNB];
 #pragma unroll
         for (int j = 0; j < PNB; ++j) {
-            double t = (j < nb) ? P[j * R + i] / sc[j] : 0.0;
+            double t = (j < nb) ? P[j * R + i] * rtmp[j] : 0.0;
 #pragma unroll
             for (int q = 0; q < j; ++q) t = fma(-y[q], Lm[j * 16 + q], t);
-            y[j] = (j < nb) ? t / Lm[j * 16 + j] : 0.0;
+            y[j] = (j < nb) ? t * rtmp[16 + j] : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < PNB; ++j)
             if (j < nb) P[j * R + i] = y[j];
     }
-    // rcur <- (L^T S) rcur
+    // rcur <- (L^T S) rcur (G is free once the Cholesky factor is in Lm)
     if (threadIdx.x < 256) {
         const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
         double t = 0.0;
         if (i <= j && j < nb)
             for (int q = i; q <= j; ++q) t = fma(Lm[q * 16 + i] * sc[q], rcur[q * 16 + j], t);
-        rtmp[threadIdx.x] = t;
+        G[threadIdx.x] = t;
     }
     __syncthreads();
-    if (threadIdx.x < 256) rcur[threadIdx.x] = rtmp[threadIdx.x];
+    if (threadIdx.x < 256) rcur[threadIdx.x] = G[threadIdx.x];
     __syncthreads();
     return true;
 }
@@ -301,7 +306,7 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
     double* coef = sc + 16;                        // 16
     double* Rm = a.R;                              // k x k, column-major: Rm[col * k + row]
     double* dv = a.d;
-    double* Q = a.Q;                               // R x k, column-major
+    double* Q = a.Q;                               // R x k, row-major: Q[i * k + c]
     __shared__ double s_rho;
     __shared__ int s_ok;
 
@@ -345,9 +350,9 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
         // ---- two projections against Q(:, 0 .. j0)
         if (j0 > 0) {
             for (int pass = 0; pass < 2; ++pass) {
-                proj_tn(Q, R, j0, P, W, red);
+                proj_tn(Q, k, R, j0, P, W, red);
                 mark(pb + 1 + 2 * pass);
-                proj_update(Q, R, j0, P, W);
+                proj_update(Q, k, R, j0, P, W);
                 for (int e = threadIdx.x; e < j0 * NB; e += LSB_NT) racc[e] += W[e];
                 __syncthreads();
                 mark(pb + 2 + 2 * pass);
@@ -434,9 +439,9 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
         }
         mark(pb + 5);
         // ---- the panel's orthonormal columns join Q; its R columns (and d)
-        for (int e = threadIdx.x; e < nb * R; e += LSB_NT) {
-            const int p = e / R, i = e - p * R;
-            if (j0 + p < kd) Q[(long long)(j0 + p) * R + i] = P[e];
+        for (int e = threadIdx.x; e < R * NB; e += LSB_NT) {
+            const int i = e / NB, p = e - i * NB;
+            if (p < nb && j0 + p < kd) Q[(long long)i * k + j0 + p] = P[p * R + i];
         }
         for (int e = threadIdx.x; e < (j0 + nb) * nb; e += LSB_NT) {
             const int c = e / nb, p = e - c * nb;
