@@ -351,7 +351,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             if constexpr (SK == SK_SPARSE) {
                 sketch_rows_partial(wt, stream == 2u ? rows2 : rows1, a.s, (double*)(part + (long long)tile * a.s));
             } else {
-                sketch_partial<TB, SK>(a, wt, a.spm, tm, stream, scale, sk, part, tile);
+                sketch_partial<TO, SK>(a, wt, a.spm, tm, stream, scale, sk, part, tile);
             }
         };
         skpart(2u, a.scz, a.zpart + par * GS);   // z_j

@@ -424,12 +424,84 @@ __device__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int b
     __syncthreads();
 }
 
+// Long rows (a wave per row): each wave takes two rows at a time and issues
+// the loads of up to 8 entries per lane of both rows before any gather, so a
+// pair of rows costs three dependent memory round trips (row pointers,
+// entries, gathers) rather than about five per row.  Per lane the entries
+// are accumulated in increasing position, then summed over the wave.
+template <typename TV, typename TX>
+__device__ void csr_tile_wave2(const int64_t* __restrict__ rp, const int* __restrict__ ci,
+                               const TV* __restrict__ cv, const TX* __restrict__ x, const Tile& ti,
+                               double* wt)
+{
+    constexpr int B = 8;                           // entries per lane per row and batch
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e0 = 2 * wave; e0 < ti.E; e0 += 2 * NWAVE) {
+        const bool two = e0 + 1 < ti.E;
+        const long long pa = rp[ti.start + e0], pm = rp[ti.start + e0 + 1];
+        const long long pb = two ? rp[ti.start + e0 + 2] : pm;
+        const long long na = pm - pa, nb = pb - pm;      // entries of row e0 and e0+1
+        double acca = 0.0, accb = 0.0;
+        for (long long b0 = 0; b0 < na || b0 < nb; b0 += 64 * B) {
+            int ca[B], cb[B];
+            TV va[B], vb[B];
+            // loads are unconditional at clamped positions (a row with no
+            // entries is skipped as a whole); values past the row are masked
+            if (na > 0) {
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const long long q = b0 + lane + 64 * u;
+                    const long long qa = pa + (q < na ? q : na - 1);
+                    ca[u] = ci[qa];
+                    const TV t = cv[qa];
+                    va[u] = q < na ? t : TV(0);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < B; ++u) { ca[u] = 0; va[u] = TV(0); }
+            }
+            if (nb > 0) {
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const long long q = b0 + lane + 64 * u;
+                    const long long qb = pm + (q < nb ? q : nb - 1);
+                    cb[u] = ci[qb];
+                    const TV t = cv[qb];
+                    vb[u] = q < nb ? t : TV(0);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < B; ++u) { cb[u] = 0; vb[u] = TV(0); }
+            }
+            TX xa[B], xb[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) { xa[u] = x[ca[u]]; xb[u] = x[cb[u]]; }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                acca = fma((double)va[u], (double)xa[u], acca);
+                accb = fma((double)vb[u], (double)xb[u], accb);
+            }
+        }
+        acca = wave_sum(acca);
+        accb = wave_sum(accb);
+        if (lane == 0) {
+            wt[e0] = acca;
+            if (two) wt[e0 + 1] = accb;
+        }
+    }
+    __syncthreads();
+}
+
 // CSR rows [start, start+E): groups of `lpr` lanes per row, FP64 accumulation.
 template <typename TV, typename TX>
 __device__ void csr_tile(const int64_t* __restrict__ rp, const int* __restrict__ ci,
                          const TV* __restrict__ cv, const TX* __restrict__ x, const Tile& ti,
                          int lpr, double* wt)
 {
+    if (lpr == 64) {
+        csr_tile_wave2<TV, TX>(rp, ci, cv, x, ti, wt);
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rpw = 64 / lpr;
     const int sub = lane / lpr, sl = lane - sub * lpr;
@@ -1101,7 +1173,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         wt[e] = elem_global(a.spm, tm, e, gi) ? (double)bvec[gi] : 0.0;
     }
     __syncthreads();
-    sketch_partial<TB, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
+    sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
     __syncthreads();
 
     // d1 = b / beta (sLSLU) or l1 = b / beta (sCMRH)
@@ -1128,7 +1200,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
             if (e < tn.E) wt[e] = ((vn >> i) & 1u) ? (double)(TB)(rect ? accn[i] / alpha : acc[i] / beta) : 0.0;
         }
         __syncthreads();
-        sketch_partial<TB, SK>(a, wt, a.spn, tn, 1u, a.scf, sk, a.fpart, tile);
+        sketch_partial<TO, SK>(a, wt, a.spn, tn, 1u, a.scf, sk, a.fpart, tile);
     }
     if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
@@ -1151,7 +1223,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
 #pragma unroll
         for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
         for (int q = threadIdx.x; q < *pm.count; q += NT) pvD[pm.list_c[q]] = wt[pm.list_e[q]];
-        sketch_partial<TB, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart, tile);
+        sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart, tile);
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
         // ---- phase B: coefficients and elimination against the data-space basis
@@ -1199,7 +1271,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
                     if (e < tm.E) wt[e] = ((vm >> i) & 1u) ? (double)(TB)(acc[i] / hv) : 0.0;
                 }
                 __syncthreads();
-                sketch_partial<TB, SK>(a, wt, a.spm, tm, 1u, a.scf, sk, a.fpart, tile);
+                sketch_partial<TO, SK>(a, wt, a.spm, tm, 1u, a.scf, sk, a.fpart, tile);
             }
             if (j + 1 == a.k) { finish(a.k, 0, a.k + 1, 0); return; }
             if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
@@ -1255,7 +1327,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
                 if (e < tn.E) wt[e] = ((vn >> i) & 1u) ? (double)(TB)(acc[i] / wv) : 0.0;
             }
             __syncthreads();
-            sketch_partial<TB, SK>(a, wt, a.spn, tn, 1u, a.scf, sk, a.fpart, tile);
+            sketch_partial<TO, SK>(a, wt, a.spn, tn, 1u, a.scf, sk, a.fpart, tile);
         }
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
     }

@@ -162,8 +162,9 @@ def compare_solve(P, g, o, bars=None):
     assert ez <= mid, f"Z differs: {ez:.3e}"
     assert ef <= mid, f"F differs: {ef:.3e}"
     assert er <= mid, f"residual history differs: {er:.3e}"
-    # S2 b depends on b only; FP32 bases generate the Gaussian entries in FP32
-    assert ec <= (1e-13 if P.basis_dtype == "f64" else 1e-6), f"S2 b differs: {ec:.3e}"
+    # S2 b depends on b only; FP32-class workloads evaluate the Gaussian
+    # entries in FP32 (about 1e-7 relative), FP64 workloads in FP64
+    assert ec <= (1e-13 if P.dtype == "f64" else 1e-6), f"S2 b differs: {ec:.3e}"
     return err
 
 
