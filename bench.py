@@ -115,7 +115,7 @@ def main():
 
     P = W.config(args.workload)
     tdt = np.float32 if P.dtype == "f32" else np.float64
-    bdt = hk.HK_F32 if P.basis_dtype == "f32" else hk.HK_F64
+    bdt = {"f64": hk.HK_F64, "f32": hk.HK_F32, "bf16": hk.HK_BF16, "f16": hk.HK_F16}[P.basis_dtype]
     ctx = hk.Context(0)
     dt = hk.HK_F32 if P.dtype == "f32" else hk.HK_F64
     if P.kind == "blur":
@@ -142,7 +142,7 @@ def main():
     it_ms, tot_ms = sv.timing_history(args.steps)
     print(f"# timed {args.steps} solves in {wall:.4f} s, status {st}", file=sys.stderr, flush=True)
 
-    w = 4 if P.basis_dtype == "f32" else 8
+    w = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[P.basis_dtype]
     ms_per_step = wall * 1e3 / args.steps
     iters = k_done * args.steps
     value = iters / wall
@@ -152,7 +152,8 @@ def main():
     if alg is not None:
         achieved = alg / (iter_avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
+                "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic() if args.workload == "c2" else None,
                 "kernel": "blur_iterate_kernel (persistent basis iteration)",
                 "alg_bytes_per_launch": alg, "avg_launch_ms": round(iter_avg, 4)}
     out = {

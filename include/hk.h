@@ -57,7 +57,12 @@ enum {
 };
 
 typedef int32_t hk_dtype;
-enum { HK_F64 = 0, HK_F32 = 1 };
+enum {
+    HK_F64 = 0,
+    HK_F32 = 1,
+    HK_BF16 = 2,   /* bfloat16 (8 significant bits); basis storage only */
+    HK_F16 = 3     /* IEEE binary16 (11 significant bits); basis storage only */
+};
 
 typedef int32_t hk_bc;     /* boundary condition of the blur */
 enum { HK_BC_ZERO = 0, HK_BC_REFLECT = 1 };
@@ -132,6 +137,17 @@ hk_status hk_op_destroy(hk_op* op);
  *           HK_F32 when the operator is FP32 as well (halves the basis bytes;
  *           all arithmetic stays FP64).  FP64 bases with an FP32 operator
  *           are allowed.  A zero-initialised struct selects HK_F64.
+ *           Reduced-precision tier: HK_BF16 or HK_F16 bases with an FP32
+ *           blur operator (b and x stay FP32).  Each new basis vector is
+ *           rounded once to the 16-bit type when stored; the operator
+ *           product, the elimination, the sketches and the small least
+ *           squares read the stored values and compute in FP64, so
+ *           z_j = S2 A l_j and f_j = S1 l_j are exact for the stored l_j and
+ *           c = S2 b uses the FP32 b.  The pivot is the argmax of the values
+ *           before rounding; the pivot entry is the rounded value.  HK_F16
+ *           needs |b| and the pivot magnitudes |H(j+1, j)| inside FP16's
+ *           range (about 6e-5 to 65504); a value that overflows makes the
+ *           solve fail with HK_ENUMERIC.
  *   flags   0, or HK_FLAG_TRACE: workgroup 0 of the basis kernel records a
  *           wall-clock timestamp before and after every grid barrier
  *           (read them with hk_solve_get_trace) */
@@ -175,7 +191,12 @@ hk_status hk_solve_wait(hk_solve* sv);
  *   Z, F, c     host: S2 A L_k (s x k), S1 L_k (s x k, zero if lambda = 0),
  *               S2 b (s), FP64 column-major
  *   basis       which = 0: L (n x (k+1)), which = 1: D (m x (k+1), sLSLU),
- *               copied to a device buffer of basis_dtype, column-major */
+ *               copied to a device buffer of basis_dtype, column-major;
+ *               which = 2: the columns of L as stored.  The single-barrier
+ *               blur kernel stores v_j = eta_j l_j unnormalised (eta_j =
+ *               v_j(t_j), the pivot entry), so l_j = v_j / v_j(t_j); which = 0
+ *               then returns l_j rounded to basis_dtype a second time.  For
+ *               the other kernels which = 2 equals which = 0. */
 hk_status hk_solve_info(hk_solve* sv, int32_t* k_done);
 hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W);
 hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g);

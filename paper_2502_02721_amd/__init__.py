@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libhk.so")
 
 HK_OK, HK_BREAKDOWN = 0, 1
 HK_EINVAL, HK_ENOMEM, HK_EDEVICE, HK_ENUMERIC, HK_EUNSUPPORTED = -1, -2, -3, -4, -5
-HK_F64, HK_F32 = 0, 1
+HK_F64, HK_F32, HK_BF16, HK_F16 = 0, 1, 2, 3
 HK_BC_ZERO, HK_BC_REFLECT = 0, 1
 HK_SKETCH_GAUSSIAN, HK_SKETCH_SPARSE_SIGN = 0, 1
 HK_METHOD_AUTO, HK_METHOD_HESSENBERG, HK_METHOD_CHANGING_HESSENBERG = 0, 1, 2
@@ -262,7 +262,7 @@ def _torch():
     return torch
 
 
-_DT = {HK_F64: "float64", HK_F32: "float32"}
+_DT = {HK_F64: "float64", HK_F32: "float32", HK_BF16: "bfloat16", HK_F16: "float16"}
 
 
 class Context:
@@ -385,7 +385,7 @@ class Solve:
 
     def basis(self, which: int = 0):
         torch = _torch()
-        length = self.op.n if which == 0 else self.op.m
+        length = self.op.m if which == 1 else self.op.n
         tdt = getattr(torch, _DT[self.basis_dtype])
         out = torch.empty((self.k + 1, length), dtype=tdt, device=f"cuda:{self.op.ctx.device}")
         hk_solve_get_basis(self.handle, which, out.data_ptr())

@@ -98,7 +98,8 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
     TB* stage = (TB*)(smem + a.lds_stage);
     double* vert = (double*)(smem + a.lds_vert);
     double* taps = (double*)(smem + a.lds_taps);
-    TB* Pl = (TB*)(smem + a.lds_pD);
+    using TP = typename PivotT<TB>::type;
+    TP* Pl = (TP*)(smem + a.lds_pD);
     double* wred = (double*)(smem + a.lds_wred);
     int* pivs = (int*)(smem + a.lds_pl_n);       // all pivots found so far
     int* wlist = (int*)(smem + a.lds_pc_n);      // pivots whose window meets this tile
@@ -222,7 +223,12 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 }
             }
             __syncthreads();
+            // The argmax compares the values before rounding to the storage
+            // type; the pivot entry eta_j is the value as stored, so that
+            // l_j = s_j v_j has l_j(p_j) = 1 up to the FP64 reciprocal for
+            // every storage type.
             eta = s_amv;
+            if constexpr (sizeof(TB) < sizeof(double)) eta = (double)(TB)eta;
             p = s_ami;
         }
         mark(j, 1);
@@ -302,7 +308,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             // consume
             if ((int)threadIdx.x < j)
-                Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TB)(sc_l[threadIdx.x] * (double)gv);
+                Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TP)(sc_l[threadIdx.x] * (double)gv);
 #pragma unroll
             for (int u = 0; u < SBW; ++u) {
                 const int q = u * NT + (int)threadIdx.x;
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         mark(j, 5);
         if (threadIdx.x == 0) pv[j] = sj * upj;
         __syncthreads();
-        if (threadIdx.x < 64) forward_subst<TB>(Pl, k, pv, j + 1, h_l);
+        if (threadIdx.x < 64) forward_subst<TP>(Pl, k, pv, j + 1, h_l);
         __syncthreads();
         mark(j, 6);
         for (int i = threadIdx.x; i <= j; i += NT) hs_l[i] = h_l[i] * sc_l[i];
@@ -356,10 +362,15 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         };
         skpart(2u, a.scz, a.zpart + par * GS);   // z_j
         mark(j, 15);
-        if (j == 0) {   // c = S2 b = S2 v_0
+        if (j == 0) {   // c = S2 b: b itself when the basis type is narrower
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
                 const int yy = e / TX, xx = e - yy * TX;
-                wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
+                if constexpr (sizeof(TB) < sizeof(TO)) {
+                    const int gy = tm.y0 + yy, gx = tm.x0 + xx;
+                    wt[e] = (gy < ny && gx < nx) ? (double)bvec[gy * nx + gx] : 0.0;
+                } else {
+                    wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
+                }
             }
             __syncthreads();
             skpart(2u, scc, a.cpart);
@@ -375,7 +386,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         __syncthreads();
         mark(j, 8);
         // v_{j+1} = u - sum_i (h_i s_i) v_i
-        eliminate<TB, EPT>(acc, gm, V, ld, hs_l, j + 1);
+        eliminate_buf<TB, EPT>(acc, gm, V, ld, hs_l, j + 1);
         mark(j, 9);
         zero_pivots<EPT>(acc, vm, pm.bits);
         tile_argmax<EPT>(acc, gm, vm, a.amv + par * G, a.ami + par * G, tile);

@@ -785,6 +785,13 @@ __device__ __forceinline__ void reduce_partials(const KArgs& a, const long long*
 // wave 0: h_c is final when column c is reached; the next column is read from
 // LDS while the current one is applied.
 // ------------------------------------------------------------------------
+// Storage of the pivot block: the basis type, except FP32 for 16-bit bases,
+// where the products s_i v_i(p_j) would otherwise be rounded a second time
+// to 8 or 11 significant bits.
+template <typename TB> struct PivotT { using type = TB; };
+template <> struct PivotT<__bf16> { using type = float; };
+template <> struct PivotT<_Float16> { using type = float; };
+
 template <typename TS, int NQ>
 __device__ __forceinline__ void forward_subst_nq(const TS* __restrict__ Pl, int k, const double* __restrict__ pv,
                                                  int nh, double* h)
@@ -911,6 +918,69 @@ __device__ __forceinline__ void eliminate(double (&acc)[EPT], const int (&gi)[EP
         TS xv[EPT];
 #pragma unroll
         for (int i = 0; i < EPT; ++i) xv[i] = *(const TS*)(col + off[i]);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) acc[i] = fma(-hu, (double)xv[i], acc[i]);
+    }
+}
+
+// One element of a basis column through a buffer resource: a 32-bit lane
+// offset plus a uniform column offset, so a batch of columns costs one VGPR
+// per element instead of a 64-bit address per load.  Loads outside the
+// resource's byte range return 0.
+template <typename TS>
+__device__ __forceinline__ TS buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    if constexpr (sizeof(TS) == 8) {
+        return __builtin_bit_cast(TS, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else if constexpr (sizeof(TS) == 4) {
+        return __builtin_bit_cast(TS, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else {
+        return __builtin_bit_cast(TS, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    }
+}
+
+// raw (unstructured) buffer resource over `bytes` bytes at p
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// The same elimination with the columns read through one buffer resource
+// (fewer address registers; the 16-bit loads of the pointer form get
+// serialised by the scheduler under register pressure).  The columns read lie
+// in the first ncols * ld elements of B (at most 2^31 bytes; the host limits
+// n and k).
+template <typename TS, int EPT>
+__device__ __forceinline__ void eliminate_buf(double (&acc)[EPT], const int (&gi)[EPT],
+                                          const TS* __restrict__ B, long long ld, const double* h,
+                                          int ncols)
+{
+    constexpr int U = (EPT == 1) ? 32 : ((EPT == 2) ? 8 : 4);
+    const unsigned ldb = (unsigned)ld * (unsigned)sizeof(TS);
+    const __amdgpu_buffer_rsrc_t rs = raw_rsrc(B, (unsigned)ncols * ldb);
+    unsigned off[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) off[i] = (unsigned)gi[i] * (unsigned)sizeof(TS);
+    int c = 0;
+    for (; c + U <= ncols; c += U) {
+        TS xv[U][EPT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) xv[u][i] = buf_load<TS>(rs, off[i], (unsigned)(c + u) * ldb);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double hu = h[c + u];
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) acc[i] = fma(-hu, (double)xv[u][i], acc[i]);
+        }
+    }
+    for (; c < ncols; ++c) {
+        const double hu = h[c];
+        TS xv[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) xv[i] = buf_load<TS>(rs, off[i], (unsigned)c * ldb);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) acc[i] = fma(-hu, (double)xv[i], acc[i]);
     }

@@ -12,6 +12,9 @@ constexpr int KMAX = 255;           // largest k: k+1 pivot slots fit 4 per lane
 constexpr int KSLOT = 4;            // (KMAX+1)/64
 constexpr int MAX_EPT = 4;          // elements per thread of a tile (tile <= 2048 elements)
 constexpr int MAXG = 256;           // workgroups of the persistent kernel (one per CU)
+// a whole basis (at most NT * MAX_EPT * MAXG elements per column, KMAX + 1
+// FP64 columns) is addressed by 32-bit byte offsets of one buffer resource
+static_assert((long long)NT * MAX_EPT * MAXG * 8 * (KMAX + 1) < (1LL << 31), "basis exceeds 2 GiB");
 
 enum OpKind { OP_BLUR = 0, OP_CSR = 1, OP_BLUR_ONEBAR = 2 };
 

@@ -174,8 +174,10 @@ const void* select_iterate_mix(int op, int sketch, int ept);
 const void* select_blur_f64(int sketch, int ept);
 const void* select_blur_f32(int sketch, int ept);
 const void* select_blur_mix(int sketch, int ept);
+const void* select_blur_h16(int tb, int sketch, int ept);
 
-// basis storage / operator storage: (f64, f64), (f32, f32), (f64, f32)
+// basis storage / operator storage: (f64, f64), (f32, f32), (f64, f32), and
+// for the single-barrier blur kernel also (bf16, f32) and (f16, f32).
 // op = OP_BLUR_ONEBAR selects the single-barrier blur kernel
 static const void* select_iterate(int tb, int to, int op, int sketch, int ept)
 {
@@ -183,6 +185,7 @@ static const void* select_iterate(int tb, int to, int op, int sketch, int ept)
         if (tb == 0 && to == 0) return select_blur_f64(sketch, ept);
         if (tb == 1 && to == 1) return select_blur_f32(sketch, ept);
         if (tb == 0 && to == 1) return select_blur_mix(sketch, ept);
+        if ((tb == 2 || tb == 3) && to == 1) return select_blur_h16(tb, sketch, ept);
         return nullptr;
     }
     if (tb == 0 && to == 0) return select_iterate_f64(op, sketch, ept);
@@ -246,6 +249,8 @@ hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st)
     if (tb == 0 && to == 0) hipLaunchKernelGGL((combine_kernel<double, double>), dim3(blocks), dim3(256), 0, st, a);
     else if (tb == 1 && to == 1) hipLaunchKernelGGL((combine_kernel<float, float>), dim3(blocks), dim3(256), 0, st, a);
     else if (tb == 0 && to == 1) hipLaunchKernelGGL((combine_kernel<double, float>), dim3(blocks), dim3(256), 0, st, a);
+    else if (tb == 2 && to == 1) hipLaunchKernelGGL((combine_kernel<__bf16, float>), dim3(blocks), dim3(256), 0, st, a);
+    else if (tb == 3 && to == 1) hipLaunchKernelGGL((combine_kernel<_Float16, float>), dim3(blocks), dim3(256), 0, st, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -268,8 +273,12 @@ hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double*
     const dim3 grid((unsigned)((len + 255) / 256), (unsigned)ncols);
     if (tb == 0)
         hipLaunchKernelGGL(scale_basis_kernel<double>, grid, dim3(256), 0, st, (const double*)src, ld, scale, len, (double*)dst);
-    else
+    else if (tb == 1)
         hipLaunchKernelGGL(scale_basis_kernel<float>, grid, dim3(256), 0, st, (const float*)src, ld, scale, len, (float*)dst);
+    else if (tb == 2)
+        hipLaunchKernelGGL(scale_basis_kernel<__bf16>, grid, dim3(256), 0, st, (const __bf16*)src, ld, scale, len, (__bf16*)dst);
+    else
+        hipLaunchKernelGGL(scale_basis_kernel<_Float16>, grid, dim3(256), 0, st, (const _Float16*)src, ld, scale, len, (_Float16*)dst);
     return hipGetLastError();
 }
 

@@ -99,7 +99,9 @@ struct hk_solve {
 
 namespace {
 
-size_t dsize(int dtype) { return dtype == HK_F64 ? 8 : 4; }
+size_t dsize(int dtype) { return dtype == HK_F64 ? 8 : (dtype == HK_F32 ? 4 : 2); }
+// LDS pivot block entries: FP32 for 16-bit bases
+size_t pdsize(int tb) { return tb == HK_F64 ? 8 : 4; }
 
 int lanes_per_row(double avg_nnz)
 {
@@ -195,7 +197,7 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
     a.lds_vert = take(sizeof(double) * (size_t)TY * SW);
     a.lds_taps = take(sizeof(double) * 2 * (2 * r + 1));
     a.lds_wred = take(sizeof(double) * (size_t)kp1 * (size_t)std::max(NWAVE, 1 + nslot_of(r, TY, TX)));
-    a.lds_pD = take(dsize(tb) * (size_t)packed_size(k));
+    a.lds_pD = take(pdsize(tb) * (size_t)packed_size(k));
     a.lds_pL = a.lds_pD;
     a.pmode = 0;
     a.lds_skt = 0;
@@ -260,6 +262,9 @@ Plan plan_solve(const hk_op* op, const hk_params* p, int rect, int max_blocks, s
                 pl.lds_total = pl.lds.lds_total;
                 pl.spx = spx_of(op->r, TX);
                 pl.nslot = nslot_of(op->r, TY, TX);
+            } else if (tb == HK_BF16 || tb == HK_F16) {
+                pl.why = "16-bit bases need the single-barrier blur kernel, whose LDS plan does not fit";
+                return pl;
             } else {
                 pl.kernel = OP_BLUR;
                 layout(pl.ept, TY, TX, op->r, OP_BLUR);
@@ -305,10 +310,12 @@ hk_status validate(const hk_op* op, const hk_params* p, int* rect)
     if (p->sketch == HK_SKETCH_SPARSE_SIGN && (p->zeta < 1 || p->zeta > p->s))
         return fail(HK_EINVAL, "zeta = %d must be in [1, s]", p->zeta);
     if (p->s > 16384) return fail(HK_EUNSUPPORTED, "sketch size s = %d exceeds 16384", p->s);
-    if (p->basis_dtype != HK_F64 && p->basis_dtype != HK_F32)
+    if (p->basis_dtype < HK_F64 || p->basis_dtype > HK_F16)
         return fail(HK_EINVAL, "unknown basis dtype %d", p->basis_dtype);
     if (p->basis_dtype == HK_F32 && op->dtype == HK_F64)
         return fail(HK_EUNSUPPORTED, "FP32 bases need an FP32 operator");
+    if ((p->basis_dtype == HK_BF16 || p->basis_dtype == HK_F16) && (op->dtype != HK_F32 || op->kind != OP_BLUR))
+        return fail(HK_EUNSUPPORTED, "16-bit bases are implemented for FP32 blur operators");
     int r = 0;
     if (p->method == HK_METHOD_AUTO) r = (op->m != op->n);
     else if (p->method == HK_METHOD_HESSENBERG) r = 0;
@@ -885,20 +892,21 @@ hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev)
     if (!dst_dev) return fail(HK_EINVAL, "null output");
     const size_t es = dsize(sv->tb);
     const int kp1 = sv->prm.k + 1;
-    if (which == 0 && sv->kernel == OP_BLUR_ONEBAR) {
+    if (which == 2 || (which == 0 && sv->kernel != OP_BLUR_ONEBAR)) {
+        // the columns as stored (unnormalised v_j for the single-barrier kernel)
+        HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->n, sv->ka.L, es * sv->ka.ldl, es * sv->op->n, kp1,
+                            hipMemcpyDeviceToDevice));
+    } else if (which == 0) {
         // stored unnormalised with per-column scales: copy l_j = s_j v_j
         HIP_TRY(launch_scale_basis(sv->tb, sv->ka.L, sv->ka.ldl, sv->ka.scale, sv->op->n, kp1, dst_dev,
                                    sv->op->ctx->stream));
         HIP_TRY(hipStreamSynchronize(sv->op->ctx->stream));
-    } else if (which == 0) {
-        HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->n, sv->ka.L, es * sv->ka.ldl, es * sv->op->n, kp1,
-                            hipMemcpyDeviceToDevice));
     } else if (which == 1) {
         if (!sv->rect) return fail(HK_EINVAL, "D exists for the generalized Hessenberg method only");
         HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->m, sv->ka.D, es * sv->ka.ldd, es * sv->op->m, kp1,
                             hipMemcpyDeviceToDevice));
     } else {
-        return fail(HK_EINVAL, "which must be 0 (L) or 1 (D)");
+        return fail(HK_EINVAL, "which must be 0 (L), 1 (D) or 2 (stored L)");
     }
     return HK_OK;
 }

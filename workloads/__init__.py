@@ -295,6 +295,7 @@ def dense_problem(name, A: np.ndarray, b: np.ndarray, k, s, lam=0.0, sketch=SKET
 # sketch (the throughput workload).  c3: 256x256 parallel-beam tomography,
 # rectangular, FP32 matrix; its bases are kept in FP64 because with lambda = 0
 # and k = 150 the solution is too sensitive to FP32 rounding of the basis.
+# c4_bf16 / c4_f16: c2 with bfloat16 / binary16 bases.
 def config(name: str) -> Problem:
     if name in ("c1", "c1_tik"):
         lam = 0.0 if name == "c1" else 1e-3
@@ -303,6 +304,10 @@ def config(name: str) -> Problem:
     if name == "c2":
         return blur_problem(name, 512, 512, 4.0, 15, BC_REFLECT, "piecewise", 0.02, k=100, s=400,
                             lam=1e-2, sketch=SKETCH_SPARSE_SIGN, zeta=8, dtype="f32", cfg_id=2)
+    if name in ("c4_bf16", "c4_f16"):
+        # the reduced-precision storage tier on the 512x512 deblurring
+        # workload: same operator and data, 16-bit Krylov bases
+        return config("c2").replace(name=name, basis=name[3:])
     if name == "c3":
         return csr_problem(name, 256, 180, 362, 0.01, k=150, s=302, lam=0.0,
                            sketch=SKETCH_GAUSSIAN, dtype="f32", cfg_id=3).replace(basis="f64")
