@@ -182,6 +182,8 @@ def solve(problem, k=None, s=None, lam=None, method=None, keep_basis=False, seed
     P = problem
     k = P.k if k is None else k
     s = P.s if s is None else s
+    if P.sketch == 3:                     # no sketch: the small problem has k+1 rows (eq. (TSP))
+        s = k + 1
     lam = P.lam if lam is None else lam
     if method is None:                    # square -> sCMRH, rectangular -> sLSLU
         method = 0 if P.m == P.n else 1

@@ -337,7 +337,8 @@ int orc_small_ls(int64_t s, int64_t k, const double* Z, const double* F, double 
 typedef struct {
     int32_t k, s;
     double lam;
-    int32_t sketch;      /* 0 Gaussian, 1 sparse sign, 2 identity [I; 0] */
+    int32_t sketch;      /* 0 Gaussian, 1 sparse sign, 2 identity [I; 0],
+                            3 none: the unsketched projected problem */
     int32_t zeta;
     uint64_t seed;
     int32_t method;      /* 0 sCMRH (square Hessenberg), 1 sLSLU (generalized) */
@@ -376,8 +377,10 @@ static int64_t pivot_search(const double* v, int64_t len, const unsigned char* u
 
 int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* out)
 {
-    const int64_t m = A->m, n = A->n, s = P->s;
     const int k = P->k;
+    const int none = (P->sketch == 3);
+    /* without a sketch the small problem has the k+1 rows of H_{k+1,k} */
+    const int64_t m = A->m, n = A->n, s = none ? k + 1 : P->s;
     const int rect = (P->method == 1);
     if (k < 1 || s < k + 1) return ORC_EINVAL;
     if (!rect && m != n) return ORC_EINVAL;
@@ -386,9 +389,10 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
 
     orc_sketch S1, S2;
     memset(&S1, 0, sizeof S1);
-    int st = sketch_make(&S2, P->sketch, s, m, P->zeta, P->seed, 2u);
+    memset(&S2, 0, sizeof S2);
+    int st = none ? ORC_OK : sketch_make(&S2, P->sketch, s, m, P->zeta, P->seed, 2u);
     if (st) return st;
-    if (P->lam > 0.0) {
+    if (P->lam > 0.0 && !none) {
         st = sketch_make(&S1, P->sketch, s, n, P->zeta, P->seed, 1u);
         if (st) { sketch_free(&S2); return st; }
     }
@@ -415,20 +419,22 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
 #define WW(i, j) out->W[(int64_t)(j) * k + (i)]
 
     int k_done = 0, nt = 0, ng = 0;
-    sketch_apply(&S2, b, c);                 /* S2 r0 with x0 = 0 */
+    double beta0 = 0.0;                      /* b(t_1): D_{k+1}^+ b = beta e_1 */
+    if (!none) sketch_apply(&S2, b, c);      /* S2 r0 with x0 = 0 */
 
     if (!rect) {
         /* ---- sCMRH: Hessenberg process with partial pivoting ---- */
         int64_t p = pivot_search(b, m, used_m);
         if (p < 0) goto small_ls;            /* b = 0: x = 0 */
         double beta = b[p];
+        beta0 = beta;
         for (int64_t r = 0; r < n; ++r) L[r] = b[r] / beta;
         tp[0] = p; used_m[p] = 1; nt = 1;
-        if (P->lam > 0.0) sketch_apply(&S1, L, F);
+        if (P->lam > 0.0 && !none) sketch_apply(&S1, L, F);
         for (int j = 0; j < k; ++j) {       /* iteration j+1 of the paper */
             const double* lj = L + (int64_t)j * n;
             orc_op_apply(A, lj, u);           /* u = A l_j */
-            sketch_apply(&S2, u, Z + (int64_t)j * s);   /* z_j = S2 u */
+            if (!none) sketch_apply(&S2, u, Z + (int64_t)j * s);   /* z_j = S2 u */
             for (int i = 0; i <= j; ++i) {    /* gathers + axpys, no inner products */
                 double h = u[tp[i]];
                 HH(i, j) = h;
@@ -443,13 +449,14 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
             double* lnext = L + (int64_t)(j + 1) * n;
             for (int64_t r = 0; r < n; ++r) lnext[r] = u[r] / hp;
             tp[j + 1] = piv; used_m[piv] = 1; nt = j + 2;
-            if (P->lam > 0.0 && j + 1 < k) sketch_apply(&S1, lnext, F + (int64_t)(j + 1) * s);
+            if (P->lam > 0.0 && j + 1 < k && !none) sketch_apply(&S1, lnext, F + (int64_t)(j + 1) * s);
         }
     } else {
         /* ---- sLSLU: generalized Hessenberg process ---- */
         int64_t p = pivot_search(b, m, used_m);
         if (p < 0) goto small_ls;
         double beta = b[p];
+        beta0 = beta;
         for (int64_t r = 0; r < m; ++r) D[r] = b[r] / beta;
         tp[0] = p; used_m[p] = 1; nt = 1;
         orc_op_apply_t(A, b, q);              /* v0 = A^T r0 */
@@ -460,11 +467,11 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
         gp[0] = p2; used_n[p2] = 1; ng = 1;
         orc_op_apply_t(A, D, q);              /* r = A^T d1; W(1,1) = r(g(1)) */
         if (out->W) WW(0, 0) = q[p2];
-        if (P->lam > 0.0) sketch_apply(&S1, L, F);
+        if (P->lam > 0.0 && !none) sketch_apply(&S1, L, F);
         for (int j = 0; j < k; ++j) {
             const double* lj = L + (int64_t)j * n;
             orc_op_apply(A, lj, u);           /* u = A l_j */
-            sketch_apply(&S2, u, Z + (int64_t)j * s);
+            if (!none) sketch_apply(&S2, u, Z + (int64_t)j * s);
             for (int i = 0; i <= j; ++i) {
                 double h = u[tp[i]];
                 HH(i, j) = h;
@@ -494,13 +501,27 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
             double* lnext = L + (int64_t)(j + 1) * n;
             for (int64_t r = 0; r < n; ++r) lnext[r] = q[r] / wp;
             gp[j + 1] = piv2; used_n[piv2] = 1; ng = j + 2;
-            if (P->lam > 0.0) sketch_apply(&S1, lnext, F + (int64_t)(j + 1) * s);
+            if (P->lam > 0.0 && !none) sketch_apply(&S1, lnext, F + (int64_t)(j + 1) * s);
         }
     }
 
 small_ls:
     out->k_done = k_done;
     for (int64_t r = 0; r < n; ++r) out->x[r] = 0.0;
+    if (none && k_done > 0) {
+        /* CMRH / LSLU (Sec. 3.1, eq. (Hessenber_LS); with Tikhonov eq. (TP)):
+         * M_{k+1}^+ (b - A L_k y) = beta e_1 - H_{k+1,k} y and
+         * L_k^+ L_k y = y, so the problem is eq. (TSP):
+         *   min ||beta e_1 - H y||^2 + lam^2 ||y||^2,
+         * the same stacked least squares with Z = H, F = [I; 0], c = beta e_1. */
+        for (int j = 0; j < k; ++j)
+            for (int64_t i = 0; i < s; ++i) {
+                Z[(int64_t)j * s + i] = out->H[(int64_t)j * kk1 + i];
+                F[(int64_t)j * s + i] = (i == j) ? 1.0 : 0.0;
+            }
+        for (int64_t i = 0; i < s; ++i) c[i] = 0.0;
+        c[0] = beta0;
+    }
     if (k_done > 0) {
         int lst = orc_small_ls(s, k_done, Z, F, P->lam, c, y, out->res);
         if (lst != ORC_OK) { st = lst; goto done; }

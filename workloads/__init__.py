@@ -30,6 +30,7 @@ BC_REFLECT = 1
 
 SKETCH_GAUSSIAN = 0
 SKETCH_SPARSE_SIGN = 1
+SKETCH_NONE = 3          # no sketch: the CMRH / LSLU projected problem
 
 
 # --------------------------------------------------------------------------
