@@ -68,7 +68,15 @@ typedef int32_t hk_bc;     /* boundary condition of the blur */
 enum { HK_BC_ZERO = 0, HK_BC_REFLECT = 1 };
 
 typedef int32_t hk_sketch;
-enum { HK_SKETCH_GAUSSIAN = 0, HK_SKETCH_SPARSE_SIGN = 1 };
+enum {
+    HK_SKETCH_GAUSSIAN = 0,
+    HK_SKETCH_SPARSE_SIGN = 1,
+    /* no sketch: the unsketched methods CMRH (square) and LSLU (rectangular)
+     * of Sec. 3.1, eq. (Hessenber_LS), with Tikhonov eq. (TP); the small
+     * problem is eq. (TSP): min ||beta e_1 - H_{k+1,k} y||^2 + lambda^2 ||y||^2
+     * with beta = b(t_1).  s and zeta are ignored (s is taken as k + 1). */
+    HK_SKETCH_NONE = 3
+};
 
 typedef int32_t hk_method;
 enum { HK_METHOD_AUTO = 0, HK_METHOD_HESSENBERG = 1, HK_METHOD_CHANGING_HESSENBERG = 2 };
@@ -187,9 +195,11 @@ hk_status hk_solve_wait(hk_solve* sv);
  *   g           host, k int64 pivots of L (sLSLU), or NULL
  *   res         host, k FP64: res[j] = minimised sketched objective
  *               (||S2(b - A L y)||^2 + lambda^2 ||S1 L y||^2)^(1/2) using the
- *               first j+1 columns; entries past k_done are 0
+ *               first j+1 columns; entries past k_done are 0.  Without a
+ *               sketch: (||beta e_1 - H y||^2 + lambda^2 ||y||^2)^(1/2)
  *   Z, F, c     host: S2 A L_k (s x k), S1 L_k (s x k, zero if lambda = 0),
- *               S2 b (s), FP64 column-major
+ *               S2 b (s), FP64 column-major.  Without a sketch (s = k + 1):
+ *               H_{k+1,k}, [I; 0] (zero if lambda = 0) and beta e_1
  *   basis       which = 0: L (n x (k+1)), which = 1: D (m x (k+1), sLSLU),
  *               copied to a device buffer of basis_dtype, column-major;
  *               which = 2: the columns of L as stored.  The single-barrier

@@ -27,7 +27,7 @@ HK_OK, HK_BREAKDOWN = 0, 1
 HK_EINVAL, HK_ENOMEM, HK_EDEVICE, HK_ENUMERIC, HK_EUNSUPPORTED = -1, -2, -3, -4, -5
 HK_F64, HK_F32, HK_BF16, HK_F16 = 0, 1, 2, 3
 HK_BC_ZERO, HK_BC_REFLECT = 0, 1
-HK_SKETCH_GAUSSIAN, HK_SKETCH_SPARSE_SIGN = 0, 1
+HK_SKETCH_GAUSSIAN, HK_SKETCH_SPARSE_SIGN, HK_SKETCH_NONE = 0, 1, 3
 HK_METHOD_AUTO, HK_METHOD_HESSENBERG, HK_METHOD_CHANGING_HESSENBERG = 0, 1, 2
 HK_FLAG_TRACE = 1
 
@@ -348,7 +348,8 @@ class Solve:
             basis_dtype = op.dtype
         self.basis_dtype = basis_dtype
         self.params = make_params(k, s, lam, sketch, zeta, seed, method, basis_dtype, flags)
-        self.k, self.s = k, s
+        # without a sketch the small problem is H_{k+1,k}: s is taken as k + 1
+        self.k, self.s = k, (k + 1 if sketch == HK_SKETCH_NONE else s)
         self.rect = (method == HK_METHOD_CHANGING_HESSENBERG) or (method == HK_METHOD_AUTO and op.m != op.n)
         self.handle = hk_solve_create(op.handle, self.params)
 

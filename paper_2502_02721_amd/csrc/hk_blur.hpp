@@ -204,7 +204,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         {
             const int r0 = (int)(((long long)tile * a.s) / G), r1 = (int)(((long long)(tile + 1) * a.s) / G);
             const int nr = r1 - r0;
-            const int ntask = (j >= 1) ? nr * ((j == 1 ? 1 : 0) + 1 + (a.lam > 0.0 ? 1 : 0)) : 0;
+            const int ntask = (j >= 1 && !a.nosk) ? nr * ((j == 1 ? 1 : 0) + 1 + (a.lam > 0.0 ? 1 : 0)) : 0;
             const int wave = threadIdx.x >> 6;
             if (wave == 0) {
                 global_argmax_wave(a.amv + prv * G, a.ami + prv * G, 0, G, &s_amv, &s_ami);
@@ -253,6 +253,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             a.scale[j] = sj;
             a.tp[j] = p;
             if (j >= 1) a.H[(long long)(j - 1) * kp1 + j] = eta;
+            else ctl->beta = eta;
         }
         if (j == k) { finish(k, 0, k + 1); return; }
         __syncthreads();
@@ -360,9 +361,9 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 sketch_partial<TO, SK>(a, wt, a.spm, tm, stream, scale, sk, part, tile);
             }
         };
-        skpart(2u, a.scz, a.zpart + par * GS);   // z_j
+        if (!a.nosk) skpart(2u, a.scz, a.zpart + par * GS);   // z_j
         mark(j, 15);
-        if (j == 0) {   // c = S2 b: b itself when the basis type is narrower
+        if (j == 0 && !a.nosk) {   // c = S2 b: b itself when the basis type is narrower
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
                 const int yy = e / TX, xx = e - yy * TX;
                 if constexpr (sizeof(TB) < sizeof(TO)) {
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             __syncthreads();
             skpart(2u, scc, a.cpart);
         }
-        if (a.lam > 0.0) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
+        if (a.lam > 0.0 && !a.nosk) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
                 const int yy = e / TX, xx = e - yy * TX;
                 wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];

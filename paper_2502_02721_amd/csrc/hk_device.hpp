@@ -1238,13 +1238,15 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
 
     // c partial = S2 b (scale from max|b| = |beta|)
     const double scc = fx_scale((double)a.m * fabs(beta) * 1.000001);
-    for (int e = threadIdx.x; e < tm.E; e += NT) {
-        int gi;
-        wt[e] = elem_global(a.spm, tm, e, gi) ? (double)bvec[gi] : 0.0;
+    if (!a.nosk) {
+        for (int e = threadIdx.x; e < tm.E; e += NT) {
+            int gi;
+            wt[e] = elem_global(a.spm, tm, e, gi) ? (double)bvec[gi] : 0.0;
+        }
+        __syncthreads();
+        sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
+        __syncthreads();
     }
-    __syncthreads();
-    sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
-    __syncthreads();
 
     // d1 = b / beta (sLSLU) or l1 = b / beta (sCMRH)
 #pragma unroll
@@ -1261,9 +1263,10 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
     if (rect) add_pivot<TB>(a.spn, tile, g1, 0, pn, PL, kp1, Lb, a.ldl);
     if (tile == 0 && threadIdx.x == 0) {
         a.tp[0] = p1;
+        ctl->beta = beta;
         if (rect) { a.gp[0] = g1; a.W[0] = alpha / beta; }
     }
-    if (a.lam > 0.0) {   // f_1 = S1 l_1
+    if (a.lam > 0.0 && !a.nosk) {   // f_1 = S1 l_1
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = threadIdx.x + i * NT;
@@ -1288,12 +1291,12 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
             if (rect) lds_append_row<TB>(PlL, a.k, (const TB*)a.PL, kp1, j);
         }
         op_forward(Lb + (long long)j * a.ldl);
-        if (j == 0) reduce_partials<SK>(a, a.cpart, inv_c, tile, a.c);
-        if (a.lam > 0.0) reduce_partials<SK>(a, a.fpart, inv_f, tile, a.F + (long long)j * a.s);
+        if (j == 0 && !a.nosk) reduce_partials<SK>(a, a.cpart, inv_c, tile, a.c);
+        if (a.lam > 0.0 && !a.nosk) reduce_partials<SK>(a, a.fpart, inv_f, tile, a.F + (long long)j * a.s);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
         for (int q = threadIdx.x; q < *pm.count; q += NT) pvD[pm.list_c[q]] = wt[pm.list_e[q]];
-        sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart, tile);
+        if (!a.nosk) sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart, tile);
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
         // ---- phase B: coefficients and elimination against the data-space basis
@@ -1308,7 +1311,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         eliminate<TB, EPT>(acc, gm, Db, ldd, h_l, nh);
         zero_pivots<EPT>(acc, vm, pm.bits);
         tile_argmax<EPT>(acc, gm, vm, a.amv, a.ami, tile);
-        reduce_partials<SK>(a, a.zpart, inv_z, tile, a.Z + (long long)j * a.s);
+        if (!a.nosk) reduce_partials<SK>(a, a.zpart, inv_z, tile, a.Z + (long long)j * a.s);
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
         // ---- phase C: pivot, normalise, store
@@ -1334,7 +1337,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         add_pivot<TB>(a.spm, tile, p, j + 1, pm, PD, kp1, Db, ldd);
 
         if (!rect) {
-            if (a.lam > 0.0 && j + 1 < a.k) {
+            if (a.lam > 0.0 && j + 1 < a.k && !a.nosk) {
 #pragma unroll
                 for (int i = 0; i < EPT; ++i) {
                     const int e = threadIdx.x + i * NT;
@@ -1390,7 +1393,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         add_pivot<TB>(a.spn, tile, g, j + 1, pn, PL, kp1, Lb, a.ldl);
-        if (a.lam > 0.0) {
+        if (a.lam > 0.0 && !a.nosk) {
 #pragma unroll
             for (int i = 0; i < EPT; ++i) {
                 const int e = threadIdx.x + i * NT;

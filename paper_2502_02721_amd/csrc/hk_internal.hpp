@@ -55,7 +55,8 @@ struct Ctl {
     int nt;              // pivots found in the data-space basis (t)
     int ng;              // pivots found in the unknowns' basis (g, sLSLU)
     int nbar;            // grid barriers passed (trace length / 2)
-    int pad[56];
+    double beta;         // first pivot entry b(t_1) (the unsketched right-hand side beta e_1)
+    int pad[54];
     CtlLine gcnt;        // XCD-leader arrivals
     CtlLine xcnt[16];    // arrivals per XCD
     CtlLine xflag[16];   // release epoch per XCD
@@ -68,6 +69,7 @@ struct KArgs {
     double lam;
     uint32_t seed_lo, seed_hi;
     int rect;                   // 1: generalized Hessenberg (sLSLU)
+    int nosk;                   // 1: no sketches (the unsketched CMRH / LSLU projected problem)
     int xcd_map;                // XCD-aware tile numbering
     int G;                      // workgroups = tiles
     const void* b;
@@ -163,6 +165,7 @@ hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KAr
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st);
 hipError_t launch_small_ls(const LsArgs& a, hipStream_t st);
 hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st);
+hipError_t launch_hess_rhs(double* F, double* c, int s, int k, double lam, const Ctl* ctl, hipStream_t st);
 hipError_t launch_apply(int dtype, int op, int ept, const ApplyArgs& a, hipStream_t st);
 hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double* scale, int64_t len,
                               int ncols, void* dst, hipStream_t st);

@@ -129,6 +129,25 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a)
     x[i] = (TO)acc;
 }
 
+// Unsketched projected problem (CMRH / LSLU): F = [I; 0] (s = k + 1 rows)
+// and c = beta e_1; Z is H itself.
+__global__ __launch_bounds__(256) void hess_rhs_kernel(double* F, double* c, int s, int k, double lam,
+                                                        const Ctl* ctl)
+{
+    for (int i = threadIdx.x; i < s; i += 256) c[i] = (i == 0) ? ctl->beta : 0.0;
+    if (lam > 0.0)
+        for (int q = threadIdx.x; q < s * k; q += 256) {
+            const int j = q / s, i = q - j * s;
+            F[q] = (i == j) ? 1.0 : 0.0;
+        }
+}
+
+hipError_t launch_hess_rhs(double* F, double* c, int s, int k, double lam, const Ctl* ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(hess_rhs_kernel, dim3(1), dim3(256), 0, st, F, c, s, k, lam, ctl);
+    return hipGetLastError();
+}
+
 __global__ void ctl_init_kernel(Ctl* ctl)
 {
     unsigned* w = (unsigned*)ctl;

@@ -303,13 +303,15 @@ hk_status validate(const hk_op* op, const hk_params* p, int* rect)
     if (p->k < 1) return fail(HK_EINVAL, "k must be >= 1 (got %d)", p->k);
     if (p->k > KMAX) return fail(HK_EUNSUPPORTED, "k = %d exceeds the supported maximum %d", p->k, KMAX);
     if (p->k > std::min(op->m, op->n)) return fail(HK_EINVAL, "k = %d exceeds min(m, n)", p->k);
-    if (p->s < p->k + 1) return fail(HK_EINVAL, "sketch size s = %d must be >= k + 1 = %d", p->s, p->k + 1);
+    if (p->sketch != HK_SKETCH_NONE && p->s < p->k + 1)
+        return fail(HK_EINVAL, "sketch size s = %d must be >= k + 1 = %d", p->s, p->k + 1);
     if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(HK_EINVAL, "lambda must be finite and >= 0");
-    if (p->sketch != HK_SKETCH_GAUSSIAN && p->sketch != HK_SKETCH_SPARSE_SIGN)
+    if (p->sketch != HK_SKETCH_GAUSSIAN && p->sketch != HK_SKETCH_SPARSE_SIGN && p->sketch != HK_SKETCH_NONE)
         return fail(HK_EINVAL, "unknown sketch type %d", p->sketch);
     if (p->sketch == HK_SKETCH_SPARSE_SIGN && (p->zeta < 1 || p->zeta > p->s))
         return fail(HK_EINVAL, "zeta = %d must be in [1, s]", p->zeta);
-    if (p->s > 16384) return fail(HK_EUNSUPPORTED, "sketch size s = %d exceeds 16384", p->s);
+    if (p->sketch != HK_SKETCH_NONE && p->s > 16384)
+        return fail(HK_EUNSUPPORTED, "sketch size s = %d exceeds 16384", p->s);
     if (p->basis_dtype < HK_F64 || p->basis_dtype > HK_F16)
         return fail(HK_EINVAL, "unknown basis dtype %d", p->basis_dtype);
     if (p->basis_dtype == HK_F32 && op->dtype == HK_F64)
@@ -326,6 +328,18 @@ hk_status validate(const hk_op* op, const hk_params* p, int* rect)
         return fail(HK_EUNSUPPORTED, "the generalized Hessenberg method needs A^T: use a CSR operator");
     *rect = r;
     return HK_OK;
+}
+
+// The parameters a solve runs with: without a sketch the small problem has
+// the k + 1 rows of H_{k+1,k}, so s = k + 1 (and no sparse-sign columns).
+hk_params effective_params(const hk_params& p)
+{
+    hk_params e = p;
+    if (e.sketch == HK_SKETCH_NONE) {
+        e.s = e.k + 1;
+        e.zeta = 0;
+    }
+    return e;
 }
 
 struct WsLayout {
@@ -651,25 +665,29 @@ static hk_status max_blocks(const hk_op* op, const hk_params* p, int rect, Plan*
     return HK_OK;
 }
 
-hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* p, size_t* bytes)
+hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* p_in, size_t* bytes)
 {
     if (!bytes) return fail(HK_EINVAL, "null output");
     int rect = 0;
-    hk_status st = validate(op, p, &rect);
+    hk_status st = validate(op, p_in, &rect);
     if (st) return st;
+    const hk_params pe = effective_params(*p_in);
+    const hk_params* p = &pe;
     Plan pl = plan_solve(op, p, rect, op->ctx->ncu, op->ctx->lds_max - 1024);
     if (!pl.ok) return fail(HK_EUNSUPPORTED, "%s", pl.why.c_str());
     *bytes = ws_layout(op, p, rect, pl.G, pl.nslot).total;
     return HK_OK;
 }
 
-hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
+hk_status hk_solve_create(hk_op* op, const hk_params* p_in, hk_solve** out)
 {
     if (!out) return fail(HK_EINVAL, "null output handle");
     *out = nullptr;
     int rect = 0;
-    hk_status st = validate(op, p, &rect);
+    hk_status st = validate(op, p_in, &rect);
     if (st) return st;
+    const hk_params pe = effective_params(*p_in);
+    const hk_params* p = &pe;
     st = current_device(op->ctx);
     if (st) return st;
     Plan pl;
@@ -710,6 +728,7 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
     a.seed_lo = (uint32_t)(p->seed & 0xffffffffu);
     a.seed_hi = (uint32_t)(p->seed >> 32);
     a.rect = rect;
+    a.nosk = (p->sketch == HK_SKETCH_NONE) ? 1 : 0;
     a.G = pl.G;
     a.xcd_map = (pl.G % 8 == 0) ? 1 : 0;
     a.spm = pl.spm;
@@ -750,7 +769,9 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
     a.trace = w.trace_cap ? (unsigned long long*)(base + w.trace) : nullptr;
     LsArgs& l = sv->la;
     l.s = p->s; l.k = p->k; l.lam = p->lambda;
-    l.Z = a.Z; l.F = a.F; l.c = a.c;
+    // unsketched: Z is H_{k+1,k} itself (column-major, leading dimension
+    // k + 1 = s); F = [I; 0] and c = beta e_1 are written before the solve
+    l.Z = a.nosk ? a.H : a.Z; l.F = a.F; l.c = a.c;
     l.Q = (double*)(base + w.Q);
     l.R = (double*)(base + w.R);
     l.r = (double*)(base + w.r);
@@ -787,6 +808,7 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
     HIP_TRY(hipEventRecord(sv->ev0, s));
     HIP_TRY(launch_iterate(sv->tb, sv->op->dtype, sv->kernel, sv->sk, sv->ept, a, s));
     HIP_TRY(hipEventRecord(sv->ev1, s));
+    if (a.nosk) HIP_TRY(launch_hess_rhs(a.F, a.c, sv->prm.s, sv->prm.k, sv->prm.lambda, a.ctl, s));
     HIP_TRY(launch_small_ls(sv->la, s));
     CombineArgs c = sv->ca;
     c.x = x_dev;
@@ -878,10 +900,11 @@ hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c)
 {
     hk_status st = ensure_done(sv);
     if (st) return st;
+    // the small problem's inputs (for the unsketched method H, [I; 0], beta e_1)
     const size_t sk = (size_t)sv->prm.s * sv->prm.k;
-    if (Z) HIP_TRY(hipMemcpy(Z, sv->ka.Z, sizeof(double) * sk, hipMemcpyDeviceToHost));
-    if (F) HIP_TRY(hipMemcpy(F, sv->ka.F, sizeof(double) * sk, hipMemcpyDeviceToHost));
-    if (c) HIP_TRY(hipMemcpy(c, sv->ka.c, sizeof(double) * sv->prm.s, hipMemcpyDeviceToHost));
+    if (Z) HIP_TRY(hipMemcpy(Z, sv->la.Z, sizeof(double) * sk, hipMemcpyDeviceToHost));
+    if (F) HIP_TRY(hipMemcpy(F, sv->la.F, sizeof(double) * sk, hipMemcpyDeviceToHost));
+    if (c) HIP_TRY(hipMemcpy(c, sv->la.c, sizeof(double) * sv->prm.s, hipMemcpyDeviceToHost));
     return HK_OK;
 }
 

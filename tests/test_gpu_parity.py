@@ -108,6 +108,32 @@ def test_scmrh_on_square_csr(hk, ctx, orc):
     _parity(hk, ctx, orc, P, method=hk.HK_METHOD_HESSENBERG)
 
 
+# ---------------------------------------------------------------- unsketched CMRH / LSLU
+# eq. (TSP) on the H the kernels build: no sketch partials, F = [I; 0],
+# c = beta e_1, the same small least-squares kernel
+@pytest.mark.parametrize("name,dtype,lam", [("blur64", "f64", 0.0), ("blur64", "f64", 1e-3),
+                                            ("ragged", "f32", 1e-2), ("deblur512", "f32", 1e-2)])
+def test_cmrh_unsketched(hk, ctx, orc, name, dtype, lam):
+    if name == "blur64":
+        P = W.config("c1").replace(lam=lam)
+    elif name == "ragged":
+        P = tiny_blur(50, 70, 1.5, 5, W.BC_REFLECT, k=25, s=60, lam=lam, dtype=dtype)
+    else:
+        P = W.config("c2")
+    _parity(hk, ctx, orc, P.replace(sketch=W.SKETCH_NONE))
+
+
+@pytest.mark.parametrize("dtype,lam", [("f64", 0.0), ("f64", 0.5), ("f32", 0.0)])
+def test_lslu_unsketched_random_csr(hk, ctx, orc, dtype, lam):
+    P = random_csr(900, 613, 0.02, k=20, s=44, lam=lam, dtype=dtype)
+    _parity(hk, ctx, orc, P.replace(sketch=W.SKETCH_NONE))
+
+
+def test_cmrh_unsketched_square_csr(hk, ctx, orc):
+    P = random_csr(500, 500, 0.03, k=30, s=62, dtype="f64")
+    _parity(hk, ctx, orc, P.replace(sketch=W.SKETCH_NONE), method=hk.HK_METHOD_HESSENBERG)
+
+
 # ---------------------------------------------------------------- edge cases
 def test_breakdown_invariant_subspace(hk, ctx, orc):
     n = 300
