@@ -40,7 +40,8 @@ class _Op(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("k", C.c_int32), ("s", C.c_int32), ("lam", C.c_double), ("sketch", C.c_int32),
-                ("zeta", C.c_int32), ("seed", C.c_uint64), ("method", C.c_int32)]
+                ("zeta", C.c_int32), ("seed", C.c_uint64), ("method", C.c_int32),
+                ("pivot_sample", C.c_int32)]
 
 
 class _Out(C.Structure):
@@ -189,7 +190,8 @@ def solve(problem, k=None, s=None, lam=None, method=None, keep_basis=False, seed
         method = 0 if P.m == P.n else 1
     op = Operator(P)
     prm = _Params(k=k, s=s, lam=lam, sketch=P.sketch, zeta=P.zeta,
-                  seed=P.seed if seed is None else seed, method=method)
+                  seed=P.seed if seed is None else seed, method=method,
+                  pivot_sample=P.pivot_sample)
     m, n = P.m, P.n
     out = {
         "x": np.zeros(n), "H": np.zeros((k + 1, k), order="F"),

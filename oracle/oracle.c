@@ -342,6 +342,7 @@ typedef struct {
     int32_t zeta;
     uint64_t seed;
     int32_t method;      /* 0 sCMRH (square Hessenberg), 1 sLSLU (generalized) */
+    int32_t pivot_sample;/* 0: full partial pivoting; m_s > 0: sampled pivoting */
 } orc_params;
 
 typedef struct {
@@ -375,8 +376,47 @@ static int64_t pivot_search(const double* v, int64_t len, const unsigned char* u
     return best;
 }
 
+/* Sampled partial pivoting (Sec. 3.2: the pivot is the largest magnitude in
+ * a small random sample of the vector's entries).  The paper does not fix
+ * the sample; the reading taken here:
+ *   - candidates come from Philox4x32-10 with counter (c, i, 3, space),
+ *     c = 0 .. nc-1, nc = ceil(m_s / 4) + 2, key (seed lo, seed hi); word w
+ *     of call c is candidate 4c + w, the row floor(w * len / 2^32);
+ *   - i is the position of the pivot being chosen in its list (t or g) and
+ *     space is 0 for t (rows of D, or of L for sCMRH) and 1 for g;
+ *   - candidates that are earlier pivots are skipped; the first m_s others
+ *     form the sample (repeats allowed);
+ *   - the pivot is the sample's largest |v(r)|, ties to the smallest r;
+ *     if the sample is empty or all zero, the full search decides, so a
+ *     breakdown is declared only when every candidate row is zero. */
+static int64_t pivot_search_sampled(const double* v, int64_t len, const unsigned char* used, int ms,
+                                    uint64_t seed, uint32_t i, uint32_t space)
+{
+    if (ms <= 0) return pivot_search(v, len, used);
+    const int nc = (ms + 3) / 4 + 2;
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    int taken = 0;
+    int64_t best = -1;
+    double bestabs = 0.0;
+    for (int c = 0; c < nc && taken < ms; ++c) {
+        const uint32_t ctr[4] = {(uint32_t)c, i, 3u, space};
+        uint32_t w[4];
+        orc_philox4x32_10(ctr, key, w);
+        for (int q = 0; q < 4 && taken < ms; ++q) {
+            const int64_t r = (int64_t)(((uint64_t)w[q] * (uint64_t)len) >> 32);
+            if (used[r]) continue;
+            ++taken;
+            const double a = fabs(v[r]);
+            if (a > bestabs || (a == bestabs && a > 0.0 && r < best)) { bestabs = a; best = r; }
+        }
+    }
+    return best >= 0 ? best : pivot_search(v, len, used);
+}
+
 int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* out)
 {
+    const int ms = P->pivot_sample;
+    const uint64_t sd = P->seed;
     const int k = P->k;
     const int none = (P->sketch == 3);
     /* without a sketch the small problem has the k+1 rows of H_{k+1,k} */
@@ -424,7 +464,7 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
 
     if (!rect) {
         /* ---- sCMRH: Hessenberg process with partial pivoting ---- */
-        int64_t p = pivot_search(b, m, used_m);
+        int64_t p = pivot_search_sampled(b, m, used_m, ms, sd, 0u, 0u);
         if (p < 0) goto small_ls;            /* b = 0: x = 0 */
         double beta = b[p];
         beta0 = beta;
@@ -442,7 +482,7 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
                 for (int64_t r = 0; r < n; ++r) u[r] = u[r] - h * li[r];
             }
             k_done = j + 1;
-            int64_t piv = (j + 1 < n) ? pivot_search(u, n, used_m) : -1;
+            int64_t piv = (j + 1 < n) ? pivot_search_sampled(u, n, used_m, ms, sd, (uint32_t)(j + 1), 0u) : -1;
             if (piv < 0) { HH(j + 1, j) = 0.0; if (j + 1 < k) st = ORC_BREAKDOWN; break; }
             double hp = u[piv];
             HH(j + 1, j) = hp;
@@ -453,14 +493,14 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
         }
     } else {
         /* ---- sLSLU: generalized Hessenberg process ---- */
-        int64_t p = pivot_search(b, m, used_m);
+        int64_t p = pivot_search_sampled(b, m, used_m, ms, sd, 0u, 0u);
         if (p < 0) goto small_ls;
         double beta = b[p];
         beta0 = beta;
         for (int64_t r = 0; r < m; ++r) D[r] = b[r] / beta;
         tp[0] = p; used_m[p] = 1; nt = 1;
         orc_op_apply_t(A, b, q);              /* v0 = A^T r0 */
-        int64_t p2 = pivot_search(q, n, used_n);
+        int64_t p2 = pivot_search_sampled(q, n, used_n, ms, sd, 0u, 1u);
         if (p2 < 0) goto small_ls;
         double alpha = q[p2];
         for (int64_t r = 0; r < n; ++r) L[r] = q[r] / alpha;
@@ -479,7 +519,7 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
                 for (int64_t r = 0; r < m; ++r) u[r] = u[r] - h * di[r];
             }
             k_done = j + 1;
-            int64_t piv = (j + 1 < m) ? pivot_search(u, m, used_m) : -1;
+            int64_t piv = (j + 1 < m) ? pivot_search_sampled(u, m, used_m, ms, sd, (uint32_t)(j + 1), 0u) : -1;
             if (piv < 0) { HH(j + 1, j) = 0.0; if (j + 1 < k) st = ORC_BREAKDOWN; break; }
             double hp = u[piv];
             HH(j + 1, j) = hp;
@@ -494,7 +534,7 @@ int orc_solve(const orc_op* A, const orc_params* P, const double* b, orc_out* ou
                 const double* li = L + (int64_t)i * n;
                 for (int64_t r = 0; r < n; ++r) q[r] = q[r] - w * li[r];
             }
-            int64_t piv2 = (j + 1 < n) ? pivot_search(q, n, used_n) : -1;
+            int64_t piv2 = (j + 1 < n) ? pivot_search_sampled(q, n, used_n, ms, sd, (uint32_t)(j + 1), 1u) : -1;
             if (piv2 < 0) { st = ORC_BREAKDOWN; break; }
             double wp = q[piv2];
             if (out->W) WW(j + 1, j + 1) = wp;

@@ -228,6 +228,7 @@ class Problem:
     col: Optional[np.ndarray] = None
     val: Optional[np.ndarray] = None
     basis: str = ""               # storage of the Krylov bases ("" = same as dtype)
+    pivot_sample: int = 0         # 0: full partial pivoting; m > 0: pivot from a sample of m rows
 
     @property
     def basis_dtype(self) -> str:
