@@ -158,7 +158,18 @@ hk_status hk_op_destroy(hk_op* op);
  *           solve fail with HK_ENUMERIC.
  *   flags   0, or HK_FLAG_TRACE: workgroup 0 of the basis kernel records a
  *           wall-clock timestamp before and after every grid barrier
- *           (read them with hk_solve_get_trace) */
+ *           (read them with hk_solve_get_trace)
+ *   pivot_sample  0: partial pivoting on the whole vector (the argmax of
+ *           |v|); 1..64: sampled pivoting (Sec. 3.2; the experiments use
+ *           5 for sCMRH and 25 for sLSLU): the pivot is the largest |v| in
+ *           a sample of that many non-pivot rows, drawn from Philox4x32-10
+ *           with counter (c, i, 3, space) and the solve's seed; word w of
+ *           call c (c < ceil(m/4) + 2) is candidate 4c + w, the row
+ *           floor(w * len / 2^32); earlier pivots are skipped, the first m
+ *           others are the sample (repeats allowed), ties go to the smaller
+ *           row.  i is the pivot's position in its list and space is 0 for
+ *           t, 1 for g.  An empty or all-zero sample falls back to the whole
+ *           vector.  Basis entries may then exceed 1 in magnitude. */
 typedef struct {
     int32_t k;
     int32_t s;
@@ -169,6 +180,7 @@ typedef struct {
     hk_method method;
     hk_dtype basis_dtype;
     uint32_t flags;
+    int32_t pivot_sample;
 } hk_params;
 
 /* Device workspace a solve of `op` with `params` holds (bases, Hessenberg

@@ -52,7 +52,8 @@ class HKError(RuntimeError):
 class hk_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("s", C.c_int32), ("lambda_", C.c_double),
                 ("sketch", C.c_int32), ("zeta", C.c_int32), ("seed", C.c_uint64),
-                ("method", C.c_int32), ("basis_dtype", C.c_int32), ("flags", C.c_uint32)]
+                ("method", C.c_int32), ("basis_dtype", C.c_int32), ("flags", C.c_uint32),
+                ("pivot_sample", C.c_int32)]
 
 
 _lib = None
@@ -173,9 +174,9 @@ def hk_op_destroy(op) -> None:
 
 
 def make_params(k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0, method=HK_METHOD_AUTO,
-                basis_dtype=HK_F64, flags=0) -> hk_params:
+                basis_dtype=HK_F64, flags=0, pivot_sample=0) -> hk_params:
     return hk_params(k=k, s=s, lambda_=lam, sketch=sketch, zeta=zeta, seed=seed, method=method,
-                     basis_dtype=basis_dtype, flags=flags)
+                     basis_dtype=basis_dtype, flags=flags, pivot_sample=pivot_sample)
 
 
 def hk_solve_workspace_bytes(op, params: hk_params) -> int:
@@ -342,12 +343,12 @@ class Solve:
     """A solve of one operator with fixed parameters; run() may be called repeatedly."""
 
     def __init__(self, op: Operator, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
-                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0):
+                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0, pivot_sample=0):
         self.op = op
         if basis_dtype is None:
             basis_dtype = op.dtype
         self.basis_dtype = basis_dtype
-        self.params = make_params(k, s, lam, sketch, zeta, seed, method, basis_dtype, flags)
+        self.params = make_params(k, s, lam, sketch, zeta, seed, method, basis_dtype, flags, pivot_sample)
         # without a sketch the small problem is H_{k+1,k}: s is taken as k + 1
         self.k, self.s = k, (k + 1 if sketch == HK_SKETCH_NONE else s)
         self.rect = (method == HK_METHOD_CHANGING_HESSENBERG) or (method == HK_METHOD_AUTO and op.m != op.n)

@@ -188,6 +188,16 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             if ((vm >> i) & 1u) V[gm[i]] = (TB)bv;
         }
         tile_argmax<EPT>(acc, gm, vm, a.amv + G, a.ami + G, tile);   // read as "previous" by step 0
+        if (a.psamp) {   // sample candidates of p_0 (values as stored)
+            for (int e = threadIdx.x; e < TY * TX; e += NT) {
+                const int yy = e / TX, xx = e - yy * TX;
+                const int gy = tm.y0 + yy, gx = tm.x0 + xx;
+                wt[e] = (gy < ny && gx < nx) ? (double)(TB)bvec[gy * nx + gx] : 0.0;
+            }
+            __syncthreads();
+            sample_publish(a.spm, tile, wt, pm.bits, a.n, a.pnc, 0u, 0u, a.seed_lo, a.seed_hi,
+                           a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS);
+        }
     }
     if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
@@ -208,6 +218,13 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             const int wave = threadIdx.x >> 6;
             if (wave == 0) {
                 global_argmax_wave(a.amv + prv * G, a.ami + prv * G, 0, G, &s_amv, &s_ami);
+                if (a.psamp) {
+                    double sv;
+                    int si;
+                    const bool ok = sample_pivot_wave(a.sval + prv * SAMPLE_SLOTS, a.sidx + prv * SAMPLE_SLOTS,
+                                                      a.pnc, a.psamp, sv, si);
+                    if (ok && threadIdx.x == 0 && s_ami != -2) { s_amv = sv; s_ami = si; }
+                }
             } else {
                 for (int t = wave - 1; t < ntask; t += NWAVE - 1) {
                     const int kind = t / nr, r = r0 + (t - kind * nr);
@@ -400,6 +417,9 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             if (e < TY * TX) wt[e] = ((vm >> i) & 1u) ? (double)vv : 0.0;
         }
         __syncthreads();
+        if (a.psamp)   // sample candidates of p_{j+1} (values as stored)
+            sample_publish(a.spm, tile, wt, pm.bits, a.n, a.pnc, (uint32_t)(j + 1), 0u, a.seed_lo, a.seed_hi,
+                           a.sval + par * SAMPLE_SLOTS, a.sidx + par * SAMPLE_SLOTS);
         mark(j, 10);
         // window sums of A v_{j+1} at the pivots p_0..p_j over this tile's
         // pixels, one wave per pivot.  A window that stays inside the image

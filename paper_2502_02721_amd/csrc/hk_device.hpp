@@ -1064,6 +1064,81 @@ __device__ void global_argmax(const double* amv, const int* ami, int off, int G,
 }
 
 // ------------------------------------------------------------------------
+// Sampled partial pivoting (Sec. 3.2: the pivot is the largest magnitude in
+// a small random sample of the vector).  Candidate q = 4c + w (c < nc) of
+// pivot search i in space sp is the row floor(word_w * len / 2^32) of the
+// Philox words of counter (c, i, 3, sp); earlier pivots are skipped and the
+// first ms other candidates form the sample (repeats allowed).  The tile that
+// owns a candidate publishes its value, or index -1 for a pivot row; after the
+// grid barrier every workgroup reads the nc * 4 slots and takes the largest
+// |value| (ties to the smaller row).  An empty or all-zero sample leaves the
+// full argmax in force.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void sample_publish(const Space& sp, int tile, const double* vals, const unsigned* bits,
+                                               int len, int nc, uint32_t i, uint32_t space, uint32_t k0,
+                                               uint32_t k1, double* sval, int* sidx)
+{
+    const int q = threadIdx.x;
+    if (q < 4 * nc) {
+        const Words w = philox10((uint32_t)(q >> 2), i, 3u, space, k0, k1);
+        const int u = q & 3;
+        const uint32_t word = u == 0 ? w.w[0] : (u == 1 ? w.w[1] : (u == 2 ? w.w[2] : w.w[3]));
+        const int r = (int)(((unsigned long long)word * (unsigned)len) >> 32);
+        int ot, oe;
+        owner_of(sp, r, ot, oe);
+        if (ot == tile) {
+            const bool piv = (bits[oe >> 5] >> (oe & 31)) & 1u;
+            sval[q] = vals[oe];
+            sidx[q] = piv ? -1 : r;
+        }
+    }
+}
+
+// Wave level: pivot of the published sample; false if it is empty or all
+// zero (the result is uniform over the wave).
+__device__ __forceinline__ bool sample_pivot_wave(const double* sval, const int* sidx, int nc, int ms,
+                                                  double& val, int& idx)
+{
+    const int lane = threadIdx.x & 63;
+    const int C = 4 * nc;                     // <= SAMPLE_SLOTS <= 128
+    const int q0 = lane, q1 = lane + 64;
+    const int c0 = min(q0, C - 1), c1 = min(q1, C - 1);
+    const int i0r = sidx[c0], i1r = sidx[c1];
+    const double v0 = sval[c0], v1 = sval[c1];
+    const int i0 = q0 < C ? i0r : -1, i1 = q1 < C ? i1r : -1;
+    const unsigned long long m0 = __ballot(i0 >= 0), m1 = __ballot(i1 >= 0);
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int r0 = __popcll(m0 & below);
+    const int r1 = __popcll(m0) + __popcll(m1 & below);
+    double best = -1.0, v = 0.0;
+    int bi = INT_MAX;
+    if (i0 >= 0 && r0 < ms && am_better(fabs(v0), i0, best, bi)) { best = fabs(v0); bi = i0; v = v0; }
+    if (i1 >= 0 && r1 < ms && am_better(fabs(v1), i1, best, bi)) { best = fabs(v1); bi = i1; v = v1; }
+    wave_argmax(best, bi, v);
+    val = v;
+    idx = bi;
+    return best > 0.0;
+}
+
+// Workgroup level: replace (val, idx) of the full argmax by the sample's
+// pivot unless the sample is empty or zero or the vector holds a non-finite
+// value (idx == -2).
+__device__ void sample_override(const double* sval, const int* sidx, int nc, int ms, double& val, int& idx)
+{
+    __shared__ double s_v;
+    __shared__ int s_i, s_ok;
+    if (threadIdx.x < 64) {
+        double v;
+        int i;
+        const bool ok = sample_pivot_wave(sval, sidx, nc, ms, v, i);
+        if (threadIdx.x == 0) { s_v = v; s_i = i; s_ok = ok ? 1 : 0; }
+    }
+    __syncthreads();
+    if (s_ok && idx != -2) { val = s_v; idx = s_i; }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------
 // per-space state kept in LDS across the whole solve
 // ------------------------------------------------------------------------
 struct PivState {
@@ -1214,21 +1289,41 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         acc[i] = ((vm >> i) & 1u) ? v : 0.0;
     }
     tile_argmax<EPT>(acc, gm, vm, a.amv, a.ami, tile);
+    // sampled pivoting: slots [0, SAMPLE_SLOTS) hold the candidates of t,
+    // [SAMPLE_SLOTS, 2 SAMPLE_SLOTS) those of g
+    auto publish = [&](const double (&v)[EPT], const Space& sp, const Tile& ti, const unsigned* bits,
+                       int len, int pos, int space) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (e < ti.E) wt[e] = v[i];
+        }
+        __syncthreads();
+        sample_publish(sp, tile, wt, bits, len, a.pnc, (uint32_t)pos, (uint32_t)space, a.seed_lo, a.seed_hi,
+                       a.sval + space * SAMPLE_SLOTS, a.sidx + space * SAMPLE_SLOTS);
+        __syncthreads();
+    };
+    if (a.psamp) publish(acc, a.spm, tm, pm.bits, a.m, 0, 0);
     if (rect) {
         if constexpr (OP == OP_CSR)                        // v0 = A^T b
             csr_tile<TO, TO>(a.rpt, a.cit, (const TO*)a.cvt, bvec, tn, a.lprt, wt);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) accn[i] = ((vn >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
         tile_argmax<EPT>(accn, gn, vn, a.amv, a.ami, G + tile);
+        if (a.psamp) publish(accn, a.spn, tn, pn.bits, a.n, 0, 1);
     }
     if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
     double beta;
     int p1;
     global_argmax(a.amv, a.ami, 0, G, beta, p1);
+    if (a.psamp) sample_override(a.sval, a.sidx, a.pnc, a.psamp, beta, p1);
     double alpha = 0.0;
     int g1 = 0;
-    if (rect) global_argmax(a.amv, a.ami, G, G, alpha, g1);
+    if (rect) {
+        global_argmax(a.amv, a.ami, G, G, alpha, g1);
+        if (a.psamp) sample_override(a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS, a.pnc, a.psamp, alpha, g1);
+    }
     if (p1 == -2 || (rect && g1 == -2)) { fail(-4); return; }
     if (beta == 0.0 || (rect && alpha == 0.0)) {
         if (tile == 0 && threadIdx.x == 0 && beta != 0.0) a.tp[0] = p1;
@@ -1312,12 +1407,17 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         zero_pivots<EPT>(acc, vm, pm.bits);
         tile_argmax<EPT>(acc, gm, vm, a.amv, a.ami, tile);
         if (!a.nosk) reduce_partials<SK>(a, a.zpart, inv_z, tile, a.Z + (long long)j * a.s);
+        if (a.psamp) {
+            __syncthreads();
+            publish(acc, a.spm, tm, pm.bits, a.m, j + 1, 0);
+        }
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
         // ---- phase C: pivot, normalise, store
         double hv;
         int p;
         global_argmax(a.amv, a.ami, 0, G, hv, p);
+        if (a.psamp) sample_override(a.sval, a.sidx, a.pnc, a.psamp, hv, p);
         if (p == -2) { fail(-4); return; }
         if (hv == 0.0 || j + 1 >= a.m) {                 // breakdown (or the space is exhausted)
             if (tile == 0 && threadIdx.x == 0) a.H[(long long)j * kp1 + j + 1] = 0.0;
@@ -1374,12 +1474,17 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         eliminate<TB, EPT>(acc, gn, Lb, a.ldl, h_l, nh);
         zero_pivots<EPT>(acc, vn, pn.bits);
         tile_argmax<EPT>(acc, gn, vn, a.amv, a.ami, tile);
+        if (a.psamp) {
+            __syncthreads();
+            publish(acc, a.spn, tn, pn.bits, a.n, j + 1, 1);
+        }
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
         // ---- phase TC: pivot of L, normalise, store, sketch S1 l_{j+1}
         double wv;
         int g;
         global_argmax(a.amv, a.ami, 0, G, wv, g);
+        if (a.psamp) sample_override(a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS, a.pnc, a.psamp, wv, g);
         if (g == -2) { fail(-4); return; }
         if (wv == 0.0 || j + 1 >= a.n) { finish(j + 1, 1, j + 2, j + 1); return; }
         if (tile == 0 && threadIdx.x == 0) {

@@ -12,6 +12,8 @@ constexpr int KMAX = 255;           // largest k: k+1 pivot slots fit 4 per lane
 constexpr int KSLOT = 4;            // (KMAX+1)/64
 constexpr int MAX_EPT = 4;          // elements per thread of a tile (tile <= 2048 elements)
 constexpr int MAXG = 256;           // workgroups of the persistent kernel (one per CU)
+constexpr int SAMPLE_MAX = 64;      // largest pivot sample
+constexpr int SAMPLE_SLOTS = 4 * ((SAMPLE_MAX + 3) / 4 + 2);   // candidate slots per search
 // a whole basis (at most NT * MAX_EPT * MAXG elements per column, KMAX + 1
 // FP64 columns) is addressed by 32-bit byte offsets of one buffer resource
 static_assert((long long)NT * MAX_EPT * MAXG * 8 * (KMAX + 1) < (1LL << 31), "basis exceeds 2 GiB");
@@ -70,6 +72,9 @@ struct KArgs {
     uint32_t seed_lo, seed_hi;
     int rect;                   // 1: generalized Hessenberg (sLSLU)
     int nosk;                   // 1: no sketches (the unsketched CMRH / LSLU projected problem)
+    int psamp, pnc;             // sampled pivoting: sample size (0: full argmax), Philox calls
+    double* sval;               // published sample values, 4 x SAMPLE_SLOTS
+    int* sidx;                  // their rows (-1: a pivot row), 4 x SAMPLE_SLOTS
     int xcd_map;                // XCD-aware tile numbering
     int G;                      // workgroups = tiles
     const void* b;

@@ -310,6 +310,8 @@ hk_status validate(const hk_op* op, const hk_params* p, int* rect)
         return fail(HK_EINVAL, "unknown sketch type %d", p->sketch);
     if (p->sketch == HK_SKETCH_SPARSE_SIGN && (p->zeta < 1 || p->zeta > p->s))
         return fail(HK_EINVAL, "zeta = %d must be in [1, s]", p->zeta);
+    if (p->pivot_sample < 0 || p->pivot_sample > SAMPLE_MAX)
+        return fail(HK_EINVAL, "pivot_sample = %d must be in [0, %d]", p->pivot_sample, SAMPLE_MAX);
     if (p->sketch != HK_SKETCH_NONE && p->s > 16384)
         return fail(HK_EUNSUPPORTED, "sketch size s = %d exceeds 16384", p->s);
     if (p->basis_dtype < HK_F64 || p->basis_dtype > HK_F16)
@@ -344,7 +346,7 @@ hk_params effective_params(const hk_params& p)
 
 struct WsLayout {
     size_t ctl, L, D, H, W, tp, gp, PD, PL, pvD, pvL, amv, ami, zpart, fpart, cpart, Z, F, c;
-    size_t Q, R, r, y, res, d, trace, scale, wpart, total;
+    size_t Q, R, r, y, res, d, trace, scale, wpart, sval, sidx, total;
     int trace_cap;
     int64_t ldl, ldd;
 };
@@ -392,6 +394,8 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
     w.trace = take(sizeof(unsigned long long) * (size_t)std::max(1, w.trace_cap + (w.trace_cap ? ARR_SLOTS + LS_TRACE : 0)));
     w.scale = take(sizeof(double) * kp1);
     w.wpart = take(sizeof(double) * 2 * (size_t)kp1 * std::max(1, nslot));
+    w.sval = take(sizeof(double) * 4 * SAMPLE_SLOTS);
+    w.sidx = take(sizeof(int) * 4 * SAMPLE_SLOTS);
     w.total = off;
     return w;
 }
@@ -729,6 +733,10 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p_in, hk_solve** out)
     a.seed_hi = (uint32_t)(p->seed >> 32);
     a.rect = rect;
     a.nosk = (p->sketch == HK_SKETCH_NONE) ? 1 : 0;
+    a.psamp = p->pivot_sample;
+    a.pnc = (p->pivot_sample + 3) / 4 + 2;
+    a.sval = (double*)(base + w.sval);
+    a.sidx = (int*)(base + w.sidx);
     a.G = pl.G;
     a.xcd_map = (pl.G % 8 == 0) ? 1 : 0;
     a.spm = pl.spm;

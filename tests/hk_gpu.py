@@ -44,7 +44,8 @@ def gpu_solve(hk, ctx, P, method=0, keep_basis=True, runs=1):
     import torch
     op = make_operator(hk, ctx, P)
     bdt = hk.HK_F64 if P.basis_dtype == "f64" else hk.HK_F32
-    sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, method, basis_dtype=bdt)
+    sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, method, basis_dtype=bdt,
+                  pivot_sample=P.pivot_sample)
     b = torch.tensor(P.b.astype(storage_np(P.dtype)), device=f"cuda:{ctx.device}")
     xs = []
     for _ in range(runs):

@@ -47,8 +47,20 @@ def test_version_and_null_argument_errors(hk):
     assert L.hk_solve_create(None, None, None) == hk.HK_EINVAL
 
 
-def test_params_struct_layout(hk):
-    # matches the C struct: int32 k, s; double lambda; int32 sketch, zeta;
-    # uint64 seed; int32 method, basis_dtype; uint32 flags
-    assert C.sizeof(hk.hk_params) == 48
-    assert hk.hk_params.lambda_.offset == 8 and hk.hk_params.seed.offset == 24
+def test_params_struct_layout(hk, tmp_path):
+    """The ctypes mirror of hk_params matches the C header, as compiled by gcc."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"hk.h\"\n"
+        "int main(void) { printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(hk_params),"
+        " offsetof(hk_params, lambda), offsetof(hk_params, seed), offsetof(hk_params, basis_dtype),"
+        " offsetof(hk_params, flags), offsetof(hk_params, pivot_sample)); return 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    P = hk.hk_params
+    assert got == [C.sizeof(P), P.lambda_.offset, P.seed.offset, P.basis_dtype.offset, P.flags.offset,
+                   P.pivot_sample.offset]

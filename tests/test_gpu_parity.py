@@ -134,6 +134,41 @@ def test_cmrh_unsketched_square_csr(hk, ctx, orc):
     _parity(hk, ctx, orc, P.replace(sketch=W.SKETCH_NONE), method=hk.HK_METHOD_HESSENBERG)
 
 
+# ---------------------------------------------------------------- sampled pivoting
+# the pivot is the largest |v| in a Philox-drawn sample of non-pivot rows
+# (5 rows for sCMRH and 25 for sLSLU in the paper's experiments)
+@pytest.mark.parametrize("name,sketch,lam,ms", [("blur64", W.SKETCH_GAUSSIAN, 0.0, 5),
+                                                ("blur64", W.SKETCH_NONE, 1e-3, 5),
+                                                ("ragged_f32", W.SKETCH_SPARSE_SIGN, 1e-2, 5),
+                                                ("ragged_f64", W.SKETCH_GAUSSIAN, 0.0, 1),
+                                                ("deblur512", W.SKETCH_SPARSE_SIGN, 1e-2, 5)])
+def test_cmrh_sampled_pivots(hk, ctx, orc, name, sketch, lam, ms):
+    if name == "blur64":
+        P = W.config("c1").replace(lam=lam)
+    elif name.startswith("ragged"):
+        P = tiny_blur(50, 70, 1.5, 5, W.BC_REFLECT, k=25, s=60, lam=lam, sketch=sketch, zeta=5,
+                      dtype=name[-3:])
+    else:
+        # FP64 basis storage: with 5-row samples the basis entries grow past 1
+        # and FP32 storage rounding, compounded over 100 columns, moves H by
+        # about 3e-3 (x still agrees to 5e-5); the sampled pivot path is
+        # checked here with the basis rounding taken out
+        P = W.config("c2").replace(basis="f64")
+    _parity(hk, ctx, orc, P.replace(sketch=sketch, lam=lam, pivot_sample=ms))
+
+
+@pytest.mark.parametrize("dtype,sketch,lam", [("f64", W.SKETCH_GAUSSIAN, 0.0), ("f64", W.SKETCH_NONE, 0.5),
+                                              ("f32", W.SKETCH_SPARSE_SIGN, 0.5)])
+def test_lslu_sampled_pivots_random_csr(hk, ctx, orc, dtype, sketch, lam):
+    P = random_csr(900, 613, 0.02, k=20, s=44, lam=lam, sketch=sketch, zeta=3, dtype=dtype)
+    _parity(hk, ctx, orc, P.replace(pivot_sample=25))
+
+
+def test_cmrh_sampled_pivots_square_csr(hk, ctx, orc):
+    P = random_csr(500, 500, 0.03, k=30, s=62, dtype="f64").replace(pivot_sample=5)
+    _parity(hk, ctx, orc, P, method=hk.HK_METHOD_HESSENBERG)
+
+
 # ---------------------------------------------------------------- edge cases
 def test_breakdown_invariant_subspace(hk, ctx, orc):
     n = 300
