@@ -283,7 +283,7 @@ __device__ __forceinline__ bool spin_until(unsigned* p, unsigned target, Ctl* ct
 }
 
 // Start-up: count the workgroups of each XCD (one flat barrier).
-__device__ bool hbar_init(Ctl* ctl, BarState& bs, unsigned G, unsigned long long timeout)
+__device__ __forceinline__ bool hbar_init(Ctl* ctl, BarState& bs, unsigned G, unsigned long long timeout)
 {
     __shared__ int s_ok;
     __shared__ unsigned s_xcd, s_pop, s_nx;
@@ -494,7 +494,7 @@ __device__ void csr_tile_wave2(const int64_t* __restrict__ rp, const int* __rest
 
 // CSR rows [start, start+E): groups of `lpr` lanes per row, FP64 accumulation.
 template <typename TV, typename TX>
-__device__ void csr_tile(const int64_t* __restrict__ rp, const int* __restrict__ ci,
+__device__ __forceinline__ void csr_tile(const int64_t* __restrict__ rp, const int* __restrict__ ci,
                          const TV* __restrict__ cv, const TX* __restrict__ x, const Tile& ti,
                          int lpr, double* wt)
 {
@@ -1052,7 +1052,7 @@ __device__ __forceinline__ void global_argmax_wave(const double* amv, const int*
     if (lane == 0) { *sv = v; *si = bad ? -2 : bi; }
 }
 
-__device__ void global_argmax(const double* amv, const int* ami, int off, int G, double& val, int& idx)
+__device__ __forceinline__ void global_argmax(const double* amv, const int* ami, int off, int G, double& val, int& idx)
 {
     __shared__ double s_val;
     __shared__ int s_idx;
@@ -1123,7 +1123,7 @@ __device__ __forceinline__ bool sample_pivot_wave(const double* sval, const int*
 // Workgroup level: replace (val, idx) of the full argmax by the sample's
 // pivot unless the sample is empty or zero or the vector holds a non-finite
 // value (idx == -2).
-__device__ void sample_override(const double* sval, const int* sidx, int nc, int ms, double& val, int& idx)
+__device__ __forceinline__ void sample_override(const double* sval, const int* sidx, int nc, int ms, double& val, int& idx)
 {
     __shared__ double s_v;
     __shared__ int s_i, s_ok;
@@ -1162,7 +1162,7 @@ __device__ __forceinline__ void zero_pivots(double (&acc)[EPT], unsigned vmask, 
 // write row col of the global, row-major pivot block (P(col, c) = B_c(p),
 // P(col, col) = 1).
 template <typename TS>
-__device__ void add_pivot(const Space& sp, int tile, int p, int col, PivState& ps, TS* P, int kp1,
+__device__ __forceinline__ void add_pivot(const Space& sp, int tile, int p, int col, PivState& ps, TS* P, int kp1,
                           const TS* B, long long ld)
 {
     int ot, oe;
@@ -1184,7 +1184,7 @@ __device__ void add_pivot(const Space& sp, int tile, int p, int col, PivState& p
 // ------------------------------------------------------------------------
 // TB: storage type of the bases; TO: storage type of the operator values,
 // of b and of x.
-template <typename TB, typename TO, int OP, int SK, int EPT>
+template <typename TB, typename TO, int OP, int SK, int EPT, bool SAMP>
 __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1303,26 +1303,26 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
                        a.sval + space * SAMPLE_SLOTS, a.sidx + space * SAMPLE_SLOTS);
         __syncthreads();
     };
-    if (a.psamp) publish(acc, a.spm, tm, pm.bits, a.m, 0, 0);
+    if constexpr (SAMP) publish(acc, a.spm, tm, pm.bits, a.m, 0, 0);
     if (rect) {
         if constexpr (OP == OP_CSR)                        // v0 = A^T b
             csr_tile<TO, TO>(a.rpt, a.cit, (const TO*)a.cvt, bvec, tn, a.lprt, wt);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) accn[i] = ((vn >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
         tile_argmax<EPT>(accn, gn, vn, a.amv, a.ami, G + tile);
-        if (a.psamp) publish(accn, a.spn, tn, pn.bits, a.n, 0, 1);
+        if constexpr (SAMP) publish(accn, a.spn, tn, pn.bits, a.n, 0, 1);
     }
     if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
     double beta;
     int p1;
     global_argmax(a.amv, a.ami, 0, G, beta, p1);
-    if (a.psamp) sample_override(a.sval, a.sidx, a.pnc, a.psamp, beta, p1);
+    if constexpr (SAMP) sample_override(a.sval, a.sidx, a.pnc, a.psamp, beta, p1);
     double alpha = 0.0;
     int g1 = 0;
     if (rect) {
         global_argmax(a.amv, a.ami, G, G, alpha, g1);
-        if (a.psamp) sample_override(a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS, a.pnc, a.psamp, alpha, g1);
+        if constexpr (SAMP) sample_override(a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS, a.pnc, a.psamp, alpha, g1);
     }
     if (p1 == -2 || (rect && g1 == -2)) { fail(-4); return; }
     if (beta == 0.0 || (rect && alpha == 0.0)) {
@@ -1407,7 +1407,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         zero_pivots<EPT>(acc, vm, pm.bits);
         tile_argmax<EPT>(acc, gm, vm, a.amv, a.ami, tile);
         if (!a.nosk) reduce_partials<SK>(a, a.zpart, inv_z, tile, a.Z + (long long)j * a.s);
-        if (a.psamp) {
+        if constexpr (SAMP) {
             __syncthreads();
             publish(acc, a.spm, tm, pm.bits, a.m, j + 1, 0);
         }
@@ -1417,7 +1417,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         double hv;
         int p;
         global_argmax(a.amv, a.ami, 0, G, hv, p);
-        if (a.psamp) sample_override(a.sval, a.sidx, a.pnc, a.psamp, hv, p);
+        if constexpr (SAMP) sample_override(a.sval, a.sidx, a.pnc, a.psamp, hv, p);
         if (p == -2) { fail(-4); return; }
         if (hv == 0.0 || j + 1 >= a.m) {                 // breakdown (or the space is exhausted)
             if (tile == 0 && threadIdx.x == 0) a.H[(long long)j * kp1 + j + 1] = 0.0;
@@ -1474,7 +1474,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         eliminate<TB, EPT>(acc, gn, Lb, a.ldl, h_l, nh);
         zero_pivots<EPT>(acc, vn, pn.bits);
         tile_argmax<EPT>(acc, gn, vn, a.amv, a.ami, tile);
-        if (a.psamp) {
+        if constexpr (SAMP) {
             __syncthreads();
             publish(acc, a.spn, tn, pn.bits, a.n, j + 1, 1);
         }
@@ -1484,7 +1484,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         double wv;
         int g;
         global_argmax(a.amv, a.ami, 0, G, wv, g);
-        if (a.psamp) sample_override(a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS, a.pnc, a.psamp, wv, g);
+        if constexpr (SAMP) sample_override(a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS, a.pnc, a.psamp, wv, g);
         if (g == -2) { fail(-4); return; }
         if (wv == 0.0 || j + 1 >= a.n) { finish(j + 1, 1, j + 2, j + 1); return; }
         if (tile == 0 && threadIdx.x == 0) {

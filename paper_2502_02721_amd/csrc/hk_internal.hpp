@@ -174,7 +174,8 @@ hipError_t launch_hess_rhs(double* F, double* c, int s, int k, double lam, const
 hipError_t launch_apply(int dtype, int op, int ept, const ApplyArgs& a, hipStream_t st);
 hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double* scale, int64_t len,
                               int ncols, void* dst, hipStream_t st);
-hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int lds_bytes, int* blocks_per_cu);
+hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int samp, int lds_bytes,
+                             int* blocks_per_cu);
 size_t small_ls_lds_bytes(int s, int k, double lam);
 int small_ls_panel(int s, int k, double lam, size_t lds_max);
 hipError_t launch_small_ls_blocked(int nb, const LsArgs& a, hipStream_t st);

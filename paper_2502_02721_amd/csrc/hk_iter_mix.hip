@@ -5,24 +5,26 @@
 namespace hk {
 
 template <int OP, int SK, int EPT>
-static const void* ptr()
+static const void* ptr(int samp)
 {
-    return (const void*)&iterate_kernel<double, float, OP, SK, EPT>;
+    return samp ? (const void*)&iterate_kernel<double, float, OP, SK, EPT, true>
+                : (const void*)&iterate_kernel<double, float, OP, SK, EPT, false>;
 }
 
 template <int OP, int SK>
-static const void* by_ept(int ept)
+static const void* by_ept(int ept, int samp)
 {
-    if (ept <= 1) return ptr<OP, SK, 1>();
-    if (ept <= 2) return ptr<OP, SK, 2>();
-    if (ept <= 4) return ptr<OP, SK, 4>();
+    if (ept <= 1) return ptr<OP, SK, 1>(samp);
+    if (ept <= 2) return ptr<OP, SK, 2>(samp);
+    if (ept <= 4) return ptr<OP, SK, 4>(samp);
     return nullptr;
 }
 
-const void* select_iterate_mix(int op, int sketch, int ept)
+const void* select_iterate_mix(int op, int sketch, int ept, int samp)
 {
-    if (op == OP_BLUR) return sketch == SK_GAUSS ? by_ept<OP_BLUR, SK_GAUSS>(ept) : by_ept<OP_BLUR, SK_SPARSE>(ept);
-    return sketch == SK_GAUSS ? by_ept<OP_CSR, SK_GAUSS>(ept) : by_ept<OP_CSR, SK_SPARSE>(ept);
+    if (op == OP_BLUR)
+        return sketch == SK_GAUSS ? by_ept<OP_BLUR, SK_GAUSS>(ept, samp) : by_ept<OP_BLUR, SK_SPARSE>(ept, samp);
+    return sketch == SK_GAUSS ? by_ept<OP_CSR, SK_GAUSS>(ept, samp) : by_ept<OP_CSR, SK_SPARSE>(ept, samp);
 }
 
 template <int SK, int EPT>

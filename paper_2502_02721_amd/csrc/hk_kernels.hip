@@ -187,9 +187,9 @@ __global__ __launch_bounds__(NT) void apply_kernel(ApplyArgs a)
 // ------------------------------------------------------------------------
 // host launchers
 // ------------------------------------------------------------------------
-const void* select_iterate_f64(int op, int sketch, int ept);
-const void* select_iterate_f32(int op, int sketch, int ept);
-const void* select_iterate_mix(int op, int sketch, int ept);
+const void* select_iterate_f64(int op, int sketch, int ept, int samp);
+const void* select_iterate_f32(int op, int sketch, int ept, int samp);
+const void* select_iterate_mix(int op, int sketch, int ept, int samp);
 const void* select_blur_f64(int sketch, int ept);
 const void* select_blur_f32(int sketch, int ept);
 const void* select_blur_mix(int sketch, int ept);
@@ -198,7 +198,9 @@ const void* select_blur_h16(int tb, int sketch, int ept);
 // basis storage / operator storage: (f64, f64), (f32, f32), (f64, f32), and
 // for the single-barrier blur kernel also (bf16, f32) and (f16, f32).
 // op = OP_BLUR_ONEBAR selects the single-barrier blur kernel
-static const void* select_iterate(int tb, int to, int op, int sketch, int ept)
+// samp: the generic kernel is instantiated with and without sampled pivoting
+// (the sampling code costs the CSR products registers when compiled in)
+static const void* select_iterate(int tb, int to, int op, int sketch, int ept, int samp)
 {
     if (op == OP_BLUR_ONEBAR) {
         if (tb == 0 && to == 0) return select_blur_f64(sketch, ept);
@@ -207,15 +209,16 @@ static const void* select_iterate(int tb, int to, int op, int sketch, int ept)
         if ((tb == 2 || tb == 3) && to == 1) return select_blur_h16(tb, sketch, ept);
         return nullptr;
     }
-    if (tb == 0 && to == 0) return select_iterate_f64(op, sketch, ept);
-    if (tb == 1 && to == 1) return select_iterate_f32(op, sketch, ept);
-    if (tb == 0 && to == 1) return select_iterate_mix(op, sketch, ept);
+    if (tb == 0 && to == 0) return select_iterate_f64(op, sketch, ept, samp);
+    if (tb == 1 && to == 1) return select_iterate_f32(op, sketch, ept, samp);
+    if (tb == 0 && to == 1) return select_iterate_mix(op, sketch, ept, samp);
     return nullptr;
 }
 
-hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int lds_bytes, int* blocks_per_cu)
+hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int samp, int lds_bytes,
+                             int* blocks_per_cu)
 {
-    const void* f = select_iterate(tb, to, op, sketch, ept);
+    const void* f = select_iterate(tb, to, op, sketch, ept, samp);
     if (!f) return hipErrorInvalidValue;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
@@ -226,7 +229,7 @@ hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int ld
 
 hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KArgs& a, hipStream_t st)
 {
-    const void* f = select_iterate(tb, to, op, sketch, ept);
+    const void* f = select_iterate(tb, to, op, sketch, ept, a.psamp > 0 ? 1 : 0);
     if (f && a.lds_total > 65536) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_total);
         if (e != hipSuccess) return e;

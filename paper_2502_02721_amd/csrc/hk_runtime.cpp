@@ -661,7 +661,7 @@ static hk_status max_blocks(const hk_op* op, const hk_params* p, int rect, Plan*
     int per_cu = 0;
     hipError_t e = iterate_occupancy(p->basis_dtype, op->dtype, pl.kernel,
                                      p->sketch == HK_SKETCH_SPARSE_SIGN ? SK_SPARSE : SK_GAUSS, pl.ept,
-                                     pl.lds_total, &per_cu);
+                                     p->pivot_sample > 0 ? 1 : 0, pl.lds_total, &per_cu);
     if (e != hipSuccess) return fail(HK_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
     if (per_cu < 1) return fail(HK_EUNSUPPORTED, "the basis kernel does not fit on a compute unit");
     if (pl.G > per_cu * ctx->ncu) return fail(HK_EUNSUPPORTED, "grid of %d exceeds co-resident capacity", pl.G);
