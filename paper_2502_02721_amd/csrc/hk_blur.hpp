@@ -288,20 +288,22 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         }
         if (j == 0) scc = fx_scale((double)a.m * fabs(eta) * 1.000001);
         mark(j, 3);
-        // Everything below depends only on p_j, so the loads of the pivot-block
-        // row (P(j, c) = l_c(p_j)), of the window partials of A v_j left by the
-        // tiles in the previous phase, and of the stencil of (A v_j)(p_j) are
-        // all issued before any is consumed.
         double* pv = wred;                                   // pv[0..j]
         double* slotv = wred + kp1;                          // partials, [i * nslot + q]
         const double* wpp = a.wpart + (long long)prv * kp1 * a.nslot;
         const TB* vj = V + (long long)j * ld;
-        double upj;
-        {
+        const int py = p / nx, px = p - py * nx;
+        const int tw2 = tw * tw;
+        const int tot = j * a.nslot;
+        // The coefficients depend only on p_j: the row of the pivot block
+        // (P(j, c) = l_c(p_j)), the window partials of A v_j left by the
+        // tiles in the previous phase and the stencil of (A v_j)(p_j).  Their
+        // first loads are all issued before any is consumed, and `middle`
+        // (the blur of the sparse-sign path) runs while they are in flight.
+        // Leaves pv[0..j] = u(p_0..p_j) in LDS.  Then h = P^{-1} u(p) by
+        // forward substitution, the same in every workgroup.
+        auto coef_loads = [&](auto&& middle) {
             constexpr int SBW = 2, SBS = 2;
-            const int tot = j * a.nslot;
-            const int py = p / nx, px = p - py * nx;
-            const int tw2 = tw * tw;
             // (a) pivot-block row: thread c < j (j <= k < NT)
             const TB gv = V[(long long)min((int)threadIdx.x, max(j - 1, 0)) * ld + p];
             // (b) first batch of window partials
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             // (c) first batch of stencil taps at p_j
             TB sv[SBS];
-            double sw[SBS];
+            int so[SBS];
 #pragma unroll
             for (int u = 0; u < SBS; ++u) {
                 const int o = u * NT + (int)threadIdx.x;
@@ -322,8 +324,9 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
                 const bool in = o < tw2 && y >= 0 && x >= 0;
                 sv[u] = vj[in ? y * nx + x : 0];
-                sw[u] = in ? tyl[aa] * txl[bb] : 0.0;
+                so[u] = in ? oc : -1;
             }
+            middle();
             // consume
             if ((int)threadIdx.x < j)
                 Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TP)(sc_l[threadIdx.x] * (double)gv);
@@ -335,52 +338,42 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             for (int q = SBW * NT + (int)threadIdx.x; q < tot; q += NT) slotv[q] = wpp[q];
             double st = 0.0;
 #pragma unroll
-            for (int u = 0; u < SBS; ++u) st = fma(sw[u], (double)sv[u], st);
+            for (int u = 0; u < SBS; ++u) {
+                if (so[u] >= 0) {
+                    const int aa = so[u] / tw, bb = so[u] - aa * tw;
+                    st = fma(tyl[aa] * txl[bb], (double)sv[u], st);
+                }
+            }
             for (int o = SBS * NT + (int)threadIdx.x; o < tw2; o += NT) {
                 const int aa = o / tw, bb = o - aa * tw;
                 const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
                 if (y >= 0 && x >= 0) st = fma(tyl[aa] * txl[bb], (double)vj[y * nx + x], st);
             }
-            upj = block_sum(st, s_red);                      // also publishes Pl and slotv
-        }
-        for (int i = threadIdx.x; i < j; i += NT) {
-            const WBox bx = wbox(pivs[i], ny, nx, r, TY, TX);
-            double sum = 0.0;
-            for (int ty = bx.tyl; ty <= bx.tyh; ++ty)
-                for (int tx = bx.txl; tx <= bx.txh; ++tx)
-                    sum += slotv[i * a.nslot + (ty - bx.tyl) * a.spx + (tx - bx.txl)];
-            pv[i] = sj * sum;
-        }
-        mark(j, 4);
-        mark(j, 5);
-        if (threadIdx.x == 0) pv[j] = sj * upj;
-        __syncthreads();
-        if (threadIdx.x < 64) forward_subst<TP>(Pl, k, pv, j + 1, h_l);
-        __syncthreads();
-        mark(j, 6);
-        for (int i = threadIdx.x; i <= j; i += NT) hs_l[i] = h_l[i] * sc_l[i];
-        if (tile == 0)
-            for (int i = threadIdx.x; i <= j; i += NT) a.H[(long long)j * kp1 + i] = h_l[i];
-        // ---- 4. the tile: u = A l_j = s_j * blur(v_j)
-        mark(j, 12);
-        blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert, wt,
-                      (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
-        mark(j, 7);
-        double acc[EPT];
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
-        for (int e = threadIdx.x; e < TY * TX; e += NT) wt[e] *= sj;
-        __syncthreads();
-        auto skpart = [&](uint32_t stream, double scale, long long* part) {
-            if constexpr (SK == SK_SPARSE) {
-                sketch_rows_partial(wt, stream == 2u ? rows2 : rows1, a.s, (double*)(part + (long long)tile * a.s));
-            } else {
-                sketch_partial<TO, SK>(a, wt, a.spm, tm, stream, scale, sk, part, tile);
+            const double upj = block_sum(st, s_red);         // also publishes Pl and slotv
+            for (int i = threadIdx.x; i < j; i += NT) {
+                const WBox bx = wbox(pivs[i], ny, nx, r, TY, TX);
+                double sum = 0.0;
+                for (int ty = bx.tyl; ty <= bx.tyh; ++ty)
+                    for (int tx = bx.txl; tx <= bx.txh; ++tx)
+                        sum += slotv[i * a.nslot + (ty - bx.tyl) * a.spx + (tx - bx.txl)];
+                pv[i] = sj * sum;
             }
+            if (threadIdx.x == 0) pv[j] = sj * upj;
+            mark(j, 4);
         };
-        if (!a.nosk) skpart(2u, a.scz, a.zpart + par * GS);   // z_j
-        mark(j, 15);
-        if (j == 0 && !a.nosk) {   // c = S2 b: b itself when the basis type is narrower
+        // wave 0: h by forward substitution, then h_i s_i and column j of H
+        auto coef_solve_wave = [&]() {
+            mark(j, 5);
+            forward_subst<TP>(Pl, k, pv, j + 1, h_l);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = threadIdx.x; i <= j; i += 64) hs_l[i] = h_l[i] * sc_l[i];
+            if (tile == 0)
+                for (int i = threadIdx.x; i <= j; i += 64) a.H[(long long)j * kp1 + i] = h_l[i];
+            mark(j, 6);
+        };
+        auto c_sketch = [&]() {   // c = S2 b: b itself when the basis type is narrower
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
                 const int yy = e / TX, xx = e - yy * TX;
                 if constexpr (sizeof(TB) < sizeof(TO)) {
@@ -391,15 +384,73 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 }
             }
             __syncthreads();
-            skpart(2u, scc, a.cpart);
-        }
-        if (a.lam > 0.0 && !a.nosk) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
+        };
+        double acc[EPT];
+        if constexpr (SK == SK_SPARSE) {
+            // ---- 4. the tile: u = A l_j = s_j * blur(v_j), with the
+            //         coefficient loads in flight; then the sketches of u
+            //         and of v_j run on waves 1..7 while wave 0 forms h
+            const bool fsk = a.lam > 0.0 && !a.nosk;
+            coef_loads([&]() {
+                mark(j, 12);
+                blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert, wt,
+                              (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
+                mark(j, 7);
+            });
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
-                const int yy = e / TX, xx = e - yy * TX;
-                wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
+                wt[e] *= sj;
+                if (fsk) {   // S1 v_j input (the vertical-pass buffer is free now)
+                    const int yy = e / TX, xx = e - yy * TX;
+                    vert[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
+                }
             }
             __syncthreads();
-            skpart(1u, scf_j, a.fpart + par * GS);
+            if (threadIdx.x < 64) {
+                coef_solve_wave();
+            } else if (!a.nosk) {
+                // z_j partial = S2 u; f_j partial = S1 v_j (scaled by s_j when reduced)
+                sketch_rows_sum(wt, rows2, a.s, (double*)(a.zpart + par * GS + (long long)tile * a.s),
+                                (int)threadIdx.x - 64, NT - 64);
+                if (fsk)
+                    sketch_rows_sum(vert, rows1, a.s, (double*)(a.fpart + par * GS + (long long)tile * a.s),
+                                    (int)threadIdx.x - 64, NT - 64);
+            }
+            __syncthreads();
+            mark(j, 15);
+            if (j == 0 && !a.nosk) {
+                c_sketch();
+                sketch_rows_partial(wt, rows2, a.s, (double*)(a.cpart + (long long)tile * a.s));
+            }
+        } else {
+            coef_loads([]() {});
+            __syncthreads();
+            if (threadIdx.x < 64) coef_solve_wave();
+            __syncthreads();
+            // ---- 4. the tile: u = A l_j = s_j * blur(v_j)
+            mark(j, 12);
+            blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert, wt,
+                          (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
+            mark(j, 7);
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
+            for (int e = threadIdx.x; e < TY * TX; e += NT) wt[e] *= sj;
+            __syncthreads();
+            if (!a.nosk) sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart + par * GS, tile);   // z_j
+            mark(j, 15);
+            if (j == 0 && !a.nosk) {
+                c_sketch();
+                sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
+            }
+            if (a.lam > 0.0 && !a.nosk) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
+                for (int e = threadIdx.x; e < TY * TX; e += NT) {
+                    const int yy = e / TX, xx = e - yy * TX;
+                    wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
+                }
+                __syncthreads();
+                sketch_partial<TO, SK>(a, wt, a.spm, tm, 1u, scf_j, sk, a.fpart + par * GS, tile);
+            }
         }
         __syncthreads();
         mark(j, 8);

@@ -349,14 +349,46 @@ __device__ __forceinline__ bool hbar_sync(Ctl* ctl, BarState& bs, unsigned long 
 // ------------------------------------------------------------------------
 // Separable blur: stage the tile plus an r-pixel halo (boundary condition
 // applied while staging), vertical pass into FP64, horizontal pass.
+constexpr int BLUR_SB = 8;                       // halo loads in flight per thread
+
+// First block of the halo loads of a tile (staged region element q of the
+// block is q0 + u * NT + thread, q0 = 0); `in` flags the loads that hit the
+// image.  Issued early, they overlap other latency.
 template <typename TS>
-__device__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int bc, const Tile& ti,
-                          int TY, int TX, const double* tyl, const double* txl, TS* stage,
-                          double* vert, double* wt, unsigned long long* tmk = nullptr)
+__device__ __forceinline__ void blur_stage_issue(const TS* __restrict__ x, int ny, int nx, int r, int bc,
+                                                 const Tile& ti, int TY, int TX, TS (&v)[BLUR_SB], unsigned& in)
 {
     const int SW = TX + 2 * r, SH = TY + 2 * r;
-    constexpr int SB = 8;                        // loads in flight per thread
-    for (int q0 = 0; q0 < SH * SW; q0 += SB * NT) {
+    in = 0u;
+#pragma unroll
+    for (int u = 0; u < BLUR_SB; ++u) {
+        const int q = u * NT + (int)threadIdx.x;
+        const int yy = q / SW, xx = q - yy * SW;
+        const int y = bc_map(ti.y0 - r + yy, ny, bc);
+        const int xg = bc_map(ti.x0 - r + xx, nx, bc);
+        const bool ok = (q < SH * SW) && y >= 0 && xg >= 0;
+        if (ok) in |= 1u << u;
+        v[u] = x[ok ? y * nx + xg : 0];
+    }
+}
+
+// Separable blur of one tile: wt = A x on the tile's pixels, with the halo
+// staged in LDS; v / in are the first block from blur_stage_issue.
+template <typename TS>
+__device__ __forceinline__ void blur_tile_staged(const TS* __restrict__ x, int ny, int nx, int r, int bc,
+                                                 const Tile& ti, int TY, int TX, const double* tyl,
+                                                 const double* txl, TS* stage, double* vert, double* wt,
+                                                 const TS (&v0)[BLUR_SB], unsigned in0,
+                                                 unsigned long long* tmk = nullptr)
+{
+    const int SW = TX + 2 * r, SH = TY + 2 * r;
+    constexpr int SB = BLUR_SB;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+        const int q = u * NT + (int)threadIdx.x;
+        if (q < SH * SW) stage[q] = ((in0 >> u) & 1u) ? v0[u] : TS(0);
+    }
+    for (int q0 = SB * NT; q0 < SH * SW; q0 += SB * NT) {
         TS v[SB];
         bool in[SB];
 #pragma unroll
@@ -422,6 +454,17 @@ __device__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int b
         if (x0 + 1 < TX) wt[yy * TX + x0 + 1] = a1;
     }
     __syncthreads();
+}
+
+template <typename TS>
+__device__ __forceinline__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int bc, const Tile& ti,
+                                          int TY, int TX, const double* tyl, const double* txl, TS* stage,
+                                          double* vert, double* wt, unsigned long long* tmk = nullptr)
+{
+    TS v[BLUR_SB];
+    unsigned in;
+    blur_stage_issue<TS>(x, ny, nx, r, bc, ti, TY, TX, v, in);
+    blur_tile_staged<TS>(x, ny, nx, r, bc, ti, TY, TX, tyl, txl, stage, vert, wt, v, in, tmk);
 }
 
 // Long rows (a wave per row): each wave takes two rows at a time and issues
@@ -688,11 +731,11 @@ __device__ void sketch_rows_build(const Space& sp, const Tile& ti, int s, int ze
     __syncthreads();
 }
 
-// out[r] = sum over the row's entries of +-vals[e], in list order (FP64).
-// Ends with a workgroup barrier.
-__device__ void sketch_rows_partial(const double* vals, SkRows t, int s, double* out)
+// out[r] = sum over the row's entries of +-vals[e], in list order (FP64),
+// rows t0, t0 + nt, ... (no barrier: callable by a subset of the waves).
+__device__ __forceinline__ void sketch_rows_sum(const double* vals, SkRows t, int s, double* out, int t0, int nt)
 {
-    for (int r = threadIdx.x; r < s; r += NT) {
+    for (int r = t0; r < s; r += nt) {
         const unsigned b = t.offs[r], en = t.offs[r + 1];
         double acc = 0.0;
         unsigned q = b;
@@ -713,6 +756,12 @@ __device__ void sketch_rows_partial(const double* vals, SkRows t, int s, double*
         }
         out[r] = acc;
     }
+}
+
+// All rows by the whole workgroup; ends with a workgroup barrier.
+__device__ void sketch_rows_partial(const double* vals, SkRows t, int s, double* out)
+{
+    sketch_rows_sum(vals, t, s, out, (int)threadIdx.x, NT);
     __syncthreads();                            // vals may be overwritten next
 }
 
