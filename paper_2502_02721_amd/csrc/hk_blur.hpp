@@ -210,6 +210,12 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         //         (waves 1 .. NWAVE-1, one row per task)
         double eta;
         int p;
+        // the first halo loads of v_j (stored before the barrier) go out
+        // here and overlap the pivot search
+        TB pre[BLUR_SB];
+        unsigned pin = 0u;
+        if constexpr (SK == SK_SPARSE)
+            blur_stage_issue<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, pre, pin);
         mark(j, 0);
         {
             const int r0 = (int)(((long long)tile * a.s) / G), r1 = (int)(((long long)(tile + 1) * a.s) / G);
@@ -393,8 +399,8 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             const bool fsk = a.lam > 0.0 && !a.nosk;
             coef_loads([&]() {
                 mark(j, 12);
-                blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert, wt,
-                              (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
+                blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert,
+                                     wt, pre, pin, (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
                 mark(j, 7);
             });
 #pragma unroll
