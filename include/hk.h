@@ -86,6 +86,7 @@ enum { HK_FLAG_TRACE = 1 };
 typedef struct hk_context hk_context;
 typedef struct hk_op hk_op;
 typedef struct hk_solve hk_solve;
+typedef struct hk_server hk_server;
 
 /* ABI version (HK_ABI_VERSION) and the thread-local last error message. */
 int32_t hk_abi_version(void);
@@ -169,7 +170,11 @@ hk_status hk_op_destroy(hk_op* op);
  *           others are the sample (repeats allowed), ties go to the smaller
  *           row.  i is the pivot's position in its list and space is 0 for
  *           t, 1 for g.  An empty or all-zero sample falls back to the whole
- *           vector.  Basis entries may then exceed 1 in magnitude. */
+ *           vector.  Basis entries may then exceed 1 in magnitude.
+ *   max_workgroups  0: the basis kernel takes one workgroup per compute
+ *           unit; > 0: at most that many (larger tiles), so that several
+ *           solves fit on the device side by side; a problem that needs
+ *           more tiles than allowed is refused with HK_EUNSUPPORTED. */
 typedef struct {
     int32_t k;
     int32_t s;
@@ -181,6 +186,7 @@ typedef struct {
     hk_dtype basis_dtype;
     uint32_t flags;
     int32_t pivot_sample;
+    int32_t max_workgroups;
 } hk_params;
 
 /* Device workspace a solve of `op` with `params` holds (bases, Hessenberg
@@ -226,6 +232,9 @@ hk_status hk_solve_get_residuals(hk_solve* sv, double* res);
 hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c);
 hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev);
 
+/* Workgroups of the solve's basis kernel (its grid; one per tile). */
+hk_status hk_solve_grid(const hk_solve* sv, int32_t* workgroups);
+
 /* Device-side duration of the last run's Hessenberg kernel and of the whole
  * run, in milliseconds (HIP events on the context stream). */
 hk_status hk_solve_timing(hk_solve* sv, double* iterate_ms, double* total_ms);
@@ -243,6 +252,45 @@ hk_status hk_solve_timing_history(hk_solve* sv, int32_t max_runs, double* iterat
 hk_status hk_solve_get_trace(hk_solve* sv, int32_t max, uint64_t* ticks, int32_t* n, double* tick_ns);
 
 hk_status hk_solve_destroy(hk_solve* sv);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of solves on one device (the benchmark spec's serving
+ * loop).  Requests are queued on arrival and admitted in arrival order as
+ * soon as a slot is free, the workspace they need fits in the device-memory
+ * budget and the compute units their basis kernel takes are free; admitted
+ * solves run on per-slot streams, side by side.  Finished requests free
+ * their slot, units and workspace (kept in a pool for reuse) for the next
+ * ones.  The server is driven by the caller's calls (submit, poll, wait);
+ * it holds no thread of its own.
+ *   slots        solves that may run at once, 1..16
+ *   budget_bytes device bytes of workspace the server may allocate (0: 80%
+ *                of the free device memory at creation)
+ *   workgroups   compute units shared by the running basis kernels (0: all
+ *                but 8, which stay free for the short kernels)
+ * A request whose params->max_workgroups is 0 gets an equal share of the
+ * units (workgroups / slots), or more if its problem needs more tiles.  The
+ * caller keeps b_dev, x_dev and the operator alive until the request has
+ * finished; its result is written to x_dev. */
+hk_status hk_server_create(hk_context* ctx, int32_t slots, size_t budget_bytes, int32_t workgroups,
+                           hk_server** out);
+hk_status hk_server_destroy(hk_server* srv);   /* waits for the running solves */
+
+/* Queue a request (returns at once with its ticket, 0, 1, 2, ...). */
+hk_status hk_server_submit(hk_server* srv, hk_op* op, const hk_params* params, const void* b_dev, void* x_dev,
+                           int64_t* ticket);
+
+/* Retire finished solves and admit queued requests; *completed = requests
+ * finished so far (may be NULL).  Does not block. */
+hk_status hk_server_poll(hk_server* srv, int64_t* completed);
+
+/* Poll until request `ticket` has finished; returns its status. */
+hk_status hk_server_wait(hk_server* srv, int64_t ticket);
+
+/* Result of a finished request: status (as hk_solve_wait), basis columns
+ * built, workgroups of its basis kernel, and host steady-clock times in
+ * seconds of its submission, admission and observed completion. */
+hk_status hk_server_result(hk_server* srv, int64_t ticket, hk_status* status, int32_t* k_done,
+                           int32_t* workgroups, double* t_submit, double* t_start, double* t_finish);
 
 #ifdef __cplusplus
 }

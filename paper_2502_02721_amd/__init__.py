@@ -38,8 +38,9 @@ ABI_FUNCTIONS = (
     "hk_op_apply", "hk_op_destroy", "hk_solve_workspace_bytes", "hk_solve_create",
     "hk_solve_run", "hk_solve_wait", "hk_solve_info", "hk_solve_get_hessenberg",
     "hk_solve_get_pivots", "hk_solve_get_residuals", "hk_solve_get_sketches",
-    "hk_solve_get_basis", "hk_solve_timing", "hk_solve_timing_history", "hk_solve_get_trace",
-    "hk_solve_destroy",
+    "hk_solve_get_basis", "hk_solve_timing", "hk_solve_grid", "hk_solve_timing_history", "hk_solve_get_trace",
+    "hk_solve_destroy", "hk_server_create", "hk_server_destroy", "hk_server_submit", "hk_server_poll",
+    "hk_server_wait", "hk_server_result",
 )
 
 
@@ -53,7 +54,7 @@ class hk_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("s", C.c_int32), ("lambda_", C.c_double),
                 ("sketch", C.c_int32), ("zeta", C.c_int32), ("seed", C.c_uint64),
                 ("method", C.c_int32), ("basis_dtype", C.c_int32), ("flags", C.c_uint32),
-                ("pivot_sample", C.c_int32)]
+                ("pivot_sample", C.c_int32), ("max_workgroups", C.c_int32)]
 
 
 _lib = None
@@ -90,9 +91,17 @@ def lib():
             "hk_solve_get_sketches": ([vp, vp, vp, vp], st),
             "hk_solve_get_basis": ([vp, i32, vp], st),
             "hk_solve_timing": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double)], st),
+            "hk_solve_grid": ([vp, C.POINTER(C.c_int32)], st),
             "hk_solve_timing_history": ([vp, i32, vp, vp, C.POINTER(i32)], st),
             "hk_solve_get_trace": ([vp, i32, vp, C.POINTER(i32), C.POINTER(C.c_double)], st),
             "hk_solve_destroy": ([vp], st),
+            "hk_server_create": ([vp, i32, C.c_size_t, i32, pp], st),
+            "hk_server_destroy": ([vp], st),
+            "hk_server_submit": ([vp, vp, vp, vp, vp, C.POINTER(i64)], st),
+            "hk_server_poll": ([vp, C.POINTER(i64)], st),
+            "hk_server_wait": ([vp, i64], st),
+            "hk_server_result": ([vp, i64, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -174,9 +183,10 @@ def hk_op_destroy(op) -> None:
 
 
 def make_params(k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0, method=HK_METHOD_AUTO,
-                basis_dtype=HK_F64, flags=0, pivot_sample=0) -> hk_params:
+                basis_dtype=HK_F64, flags=0, pivot_sample=0, max_workgroups=0) -> hk_params:
     return hk_params(k=k, s=s, lambda_=lam, sketch=sketch, zeta=zeta, seed=seed, method=method,
-                     basis_dtype=basis_dtype, flags=flags, pivot_sample=pivot_sample)
+                     basis_dtype=basis_dtype, flags=flags, pivot_sample=pivot_sample,
+                     max_workgroups=max_workgroups)
 
 
 def hk_solve_workspace_bytes(op, params: hk_params) -> int:
@@ -233,6 +243,12 @@ def hk_solve_get_sketches(sv, s: int, k: int):
 
 def hk_solve_get_basis(sv, which: int, dst_ptr: int) -> None:
     _check(lib().hk_solve_get_basis(C.c_void_p(sv), which, C.c_void_p(dst_ptr)))
+
+
+def hk_solve_grid(sv) -> int:
+    g = C.c_int32()
+    _check(lib().hk_solve_grid(C.c_void_p(sv), C.byref(g)))
+    return g.value
 
 
 def hk_solve_timing(sv):
@@ -343,12 +359,13 @@ class Solve:
     """A solve of one operator with fixed parameters; run() may be called repeatedly."""
 
     def __init__(self, op: Operator, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
-                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0, pivot_sample=0):
+                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0, pivot_sample=0, max_workgroups=0):
         self.op = op
         if basis_dtype is None:
             basis_dtype = op.dtype
         self.basis_dtype = basis_dtype
-        self.params = make_params(k, s, lam, sketch, zeta, seed, method, basis_dtype, flags, pivot_sample)
+        self.params = make_params(k, s, lam, sketch, zeta, seed, method, basis_dtype, flags, pivot_sample,
+                                  max_workgroups)
         # without a sketch the small problem is H_{k+1,k}: s is taken as k + 1
         self.k, self.s = k, (k + 1 if sketch == HK_SKETCH_NONE else s)
         self.rect = (method == HK_METHOD_CHANGING_HESSENBERG) or (method == HK_METHOD_AUTO and op.m != op.n)
@@ -396,6 +413,9 @@ class Solve:
     def timing(self):
         return hk_solve_timing(self.handle)
 
+    def grid(self) -> int:
+        return hk_solve_grid(self.handle)
+
     def trace(self):
         """Per-barrier (arrive, release) timestamps of workgroup 0, in ns."""
         t, ns = hk_solve_get_trace(self.handle)
@@ -408,6 +428,62 @@ class Solve:
         if self.handle:
             hk_solve_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching of solves on one device (argument marshalling only;
+    admission, streams and workspaces are managed by hk_server_* in the
+    library).  Keeps the tensors of each request alive until it finishes."""
+
+    def __init__(self, ctx: Context, slots: int = 4, budget_bytes: int = 0, workgroups: int = 0):
+        h = C.c_void_p()
+        _check(lib().hk_server_create(C.c_void_p(ctx.handle), slots, budget_bytes, workgroups, C.byref(h)))
+        self.ctx, self.handle = ctx, h.value
+        self._live = {}
+
+    def submit(self, op: Operator, b, x, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
+               method=HK_METHOD_AUTO, basis_dtype=None, pivot_sample=0, max_workgroups=0) -> int:
+        op._vec(b, op.m, "b")
+        op._vec(x, op.n, "x")
+        prm = make_params(k, s, lam, sketch, zeta, seed, method, op.dtype if basis_dtype is None else basis_dtype,
+                          0, pivot_sample, max_workgroups)
+        t = C.c_int64()
+        _check(lib().hk_server_submit(C.c_void_p(self.handle), C.c_void_p(op.handle), C.byref(prm),
+                                      C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(t)))
+        self._live[t.value] = (op, b, x)
+        return t.value
+
+    def poll(self) -> int:
+        n = C.c_int64()
+        _check(lib().hk_server_poll(C.c_void_p(self.handle), C.byref(n)))
+        return n.value
+
+    def wait(self, ticket: int) -> int:
+        st = lib().hk_server_wait(C.c_void_p(self.handle), ticket)
+        if st < 0:
+            raise HKError(st, lib().hk_last_error().decode())
+        return st
+
+    def result(self, ticket: int) -> dict:
+        st, kd, g = C.c_int32(), C.c_int32(), C.c_int32()
+        t0, t1, t2 = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().hk_server_result(C.c_void_p(self.handle), ticket, C.byref(st), C.byref(kd), C.byref(g),
+                                      C.byref(t0), C.byref(t1), C.byref(t2)))
+        self._live.pop(ticket, None)
+        return {"status": st.value, "k_done": kd.value, "workgroups": g.value, "t_submit": t0.value,
+                "t_start": t1.value, "t_finish": t2.value}
+
+    def close(self):
+        if self.handle:
+            _check(lib().hk_server_destroy(C.c_void_p(self.handle)))
+            self.handle = None
+            self._live.clear()
 
     def __del__(self):
         try:

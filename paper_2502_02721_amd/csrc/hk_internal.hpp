@@ -72,6 +72,7 @@ struct KArgs {
     uint32_t seed_lo, seed_hi;
     int rect;                   // 1: generalized Hessenberg (sLSLU)
     int nosk;                   // 1: no sketches (the unsketched CMRH / LSLU projected problem)
+    int coop;                   // 1: cooperative launch (whole-device grid)
     int psamp, pnc;             // sampled pivoting: sample size (0: full argmax), Philox calls
     double* sval;               // published sample values, 4 x SAMPLE_SLOTS
     int* sidx;                  // their rows (-1: a pivot row), 4 x SAMPLE_SLOTS

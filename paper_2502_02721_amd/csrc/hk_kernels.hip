@@ -237,7 +237,14 @@ hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KAr
     if (!f) return hipErrorInvalidValue;
     KArgs args = a;
     void* kargs[] = {&args};
-    return hipLaunchCooperativeKernel(f, dim3(a.G), dim3(NT), kargs, (unsigned)a.lds_total, st);
+    // A cooperative launch guarantees that the whole grid is resident, but
+    // such launches do not run side by side.  A capped grid (a.coop == 0) is
+    // launched as an ordinary kernel: its workgroups are co-resident as long
+    // as the grids running at once fit on the device (one workgroup per
+    // compute unit), which the caller keeps; the grid barrier's time-out
+    // turns a violation into an error instead of a hang.
+    if (a.coop) return hipLaunchCooperativeKernel(f, dim3(a.G), dim3(NT), kargs, (unsigned)a.lds_total, st);
+    return hipLaunchKernel(f, dim3(a.G), dim3(NT), kargs, (unsigned)a.lds_total, st);
 }
 
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st)

@@ -8,6 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <thread>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -86,8 +89,11 @@ struct hk_solve {
     KArgs ka{};
     LsArgs la{};
     CombineArgs ca{};
-    static constexpr int NEV = 256;        // runs whose events are kept
+    static constexpr int NEV = 256;        // runs whose events are kept (at most)
+    int nev = NEV;                         // event slots created
     hipEvent_t ev[NEV][3] = {};
+    hipStream_t stream = nullptr;          // where runs are ordered
+    bool own_ws = true;                    // the workspace was allocated here
     long long runs = 0;                    // runs launched
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;   // of the last run
     bool ran = false;
@@ -310,6 +316,7 @@ hk_status validate(const hk_op* op, const hk_params* p, int* rect)
         return fail(HK_EINVAL, "unknown sketch type %d", p->sketch);
     if (p->sketch == HK_SKETCH_SPARSE_SIGN && (p->zeta < 1 || p->zeta > p->s))
         return fail(HK_EINVAL, "zeta = %d must be in [1, s]", p->zeta);
+    if (p->max_workgroups < 0) return fail(HK_EINVAL, "max_workgroups must be >= 0");
     if (p->pivot_sample < 0 || p->pivot_sample > SAMPLE_MAX)
         return fail(HK_EINVAL, "pivot_sample = %d must be in [0, %d]", p->pivot_sample, SAMPLE_MAX);
     if (p->sketch != HK_SKETCH_NONE && p->s > 16384)
@@ -330,6 +337,13 @@ hk_status validate(const hk_op* op, const hk_params* p, int* rect)
         return fail(HK_EUNSUPPORTED, "the generalized Hessenberg method needs A^T: use a CSR operator");
     *rect = r;
     return HK_OK;
+}
+
+// Workgroups the basis kernel may use: the compute units, or fewer when the
+// caller caps the grid (so that several solves can run side by side).
+int grid_cap(const hk_context* ctx, const hk_params* p)
+{
+    return p->max_workgroups > 0 ? std::min(ctx->ncu, p->max_workgroups) : ctx->ncu;
 }
 
 // The parameters a solve runs with: without a sketch the small problem has
@@ -654,7 +668,7 @@ static hk_status max_blocks(const hk_op* op, const hk_params* p, int rect, Plan*
 {
     // probe occupancy with the LDS of the plan at #CU blocks; shrink if needed
     const hk_context* ctx = op->ctx;
-    Plan pl = plan_solve(op, p, rect, ctx->ncu, ctx->lds_max - 1024);   // 1 KB: static LDS of the kernels
+    Plan pl = plan_solve(op, p, rect, grid_cap(ctx, p), ctx->lds_max - 1024);   // 1 KB: static LDS of the kernels
     if (!pl.ok) return fail(HK_EUNSUPPORTED, "%s", pl.why.c_str());
     if ((size_t)pl.lds_total > ctx->lds_max)
         return fail(HK_EUNSUPPORTED, "LDS need %d B exceeds the device limit %zu B", pl.lds_total, ctx->lds_max);
@@ -677,27 +691,45 @@ hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* p_in, size_
     if (st) return st;
     const hk_params pe = effective_params(*p_in);
     const hk_params* p = &pe;
-    Plan pl = plan_solve(op, p, rect, op->ctx->ncu, op->ctx->lds_max - 1024);
+    Plan pl = plan_solve(op, p, rect, grid_cap(op->ctx, p), op->ctx->lds_max - 1024);
     if (!pl.ok) return fail(HK_EUNSUPPORTED, "%s", pl.why.c_str());
     *bytes = ws_layout(op, p, rect, pl.G, pl.nslot).total;
     return HK_OK;
 }
 
-hk_status hk_solve_create(hk_op* op, const hk_params* p_in, hk_solve** out)
+}  // extern "C"
+
+// Plan a solve: validated effective parameters, tiling and workspace size.
+static hk_status solve_plan(hk_op* op, const hk_params* p_in, hk_params* pe, int* rect, Plan* pl, size_t* bytes)
+{
+    hk_status st = validate(op, p_in, rect);
+    if (st) return st;
+    *pe = effective_params(*p_in);
+    st = current_device(op->ctx);
+    if (st) return st;
+    st = max_blocks(op, pe, *rect, pl);
+    if (st) return st;
+    *bytes = ws_layout(op, pe, *rect, pl->G, pl->nslot).total;
+    return HK_OK;
+}
+
+// Create a solve.  ws: a device buffer of at least the planned size to use
+// as workspace (zeroed on `stream`), or null to allocate one; nev: runs whose
+// timing events are kept; stream: where runs are ordered.
+static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t ws_cap, int nev,
+                              hipStream_t stream, hk_solve** out)
 {
     if (!out) return fail(HK_EINVAL, "null output handle");
     *out = nullptr;
     int rect = 0;
-    hk_status st = validate(op, p_in, &rect);
-    if (st) return st;
-    const hk_params pe = effective_params(*p_in);
-    const hk_params* p = &pe;
-    st = current_device(op->ctx);
-    if (st) return st;
+    hk_params pe{};
     Plan pl;
-    st = max_blocks(op, p, rect, &pl);
+    size_t need = 0;
+    hk_status st = solve_plan(op, p_in, &pe, &rect, &pl, &need);
     if (st) return st;
+    const hk_params* p = &pe;
     const WsLayout w = ws_layout(op, p, rect, pl.G, pl.nslot);
+    if (ws && ws_cap < w.total) return fail(HK_ENOMEM, "workspace of %zu bytes is smaller than %zu", ws_cap, w.total);
     auto* sv = new (std::nothrow) hk_solve;
     if (!sv) return fail(HK_ENOMEM, "host allocation failed");
     sv->op = op;
@@ -708,21 +740,27 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p_in, hk_solve** out)
     sv->ept = pl.ept;
     sv->kernel = pl.kernel;
     sv->G = pl.G;
-    if (hipMalloc(&sv->ws, w.total) != hipSuccess) {
+    sv->stream = stream;
+    sv->nev = std::max(1, std::min(nev, (int)hk_solve::NEV));
+    if (ws) {
+        sv->ws = ws;
+        sv->own_ws = false;
+    } else if (hipMalloc(&sv->ws, w.total) != hipSuccess) {
         delete sv;
         return fail(HK_ENOMEM, "hipMalloc of %zu workspace bytes failed", w.total);
     }
     sv->ws_bytes = w.total;
-    for (int i = 0; i < hk_solve::NEV; ++i)
+    for (int i = 0; i < sv->nev; ++i)
         for (int q = 0; q < 3; ++q)
             if (hipEventCreate(&sv->ev[i][q]) != hipSuccess) {
                 hk_solve_destroy(sv);
                 return fail(HK_EDEVICE, "hipEventCreate failed");
             }
     // zero the workspace once (H, W, pivots read back even when unused)
-    if (hipMemset(sv->ws, 0, w.total) != hipSuccess) {
+    const hipError_t ze = sv->own_ws ? hipMemset(sv->ws, 0, w.total) : hipMemsetAsync(sv->ws, 0, w.total, stream);
+    if (ze != hipSuccess) {
         hk_solve_destroy(sv);
-        return fail(HK_EDEVICE, "hipMemset failed");
+        return fail(HK_EDEVICE, "zeroing the workspace failed");
     }
     unsigned char* base = (unsigned char*)sv->ws;
     KArgs& a = sv->ka;
@@ -733,6 +771,7 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p_in, hk_solve** out)
     a.seed_hi = (uint32_t)(p->seed >> 32);
     a.rect = rect;
     a.nosk = (p->sketch == HK_SKETCH_NONE) ? 1 : 0;
+    a.coop = p->max_workgroups > 0 ? 0 : 1;
     a.psamp = p->pivot_sample;
     a.pnc = (p->pivot_sample + 3) / 4 + 2;
     a.sval = (double*)(base + w.sval);
@@ -800,15 +839,23 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p_in, hk_solve** out)
     return HK_OK;
 }
 
+extern "C" {
+
+hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
+{
+    if (!op) return fail(HK_EINVAL, "null operator");
+    return solve_create(op, p, nullptr, 0, hk_solve::NEV, op->ctx->stream, out);
+}
+
 hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
 {
     if (!sv || !b_dev || !x_dev) return fail(HK_EINVAL, "null argument");
     hk_status st = current_device(sv->op->ctx);
     if (st) return st;
-    hipStream_t s = sv->op->ctx->stream;
+    hipStream_t s = sv->stream;
     KArgs a = sv->ka;
     a.b = b_dev;
-    const int slot = (int)(sv->runs % hk_solve::NEV);
+    const int slot = (int)(sv->runs % sv->nev);
     sv->ev0 = sv->ev[slot][0];
     sv->ev1 = sv->ev[slot][1];
     sv->ev2 = sv->ev[slot][2];
@@ -930,8 +977,8 @@ hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev)
     } else if (which == 0) {
         // stored unnormalised with per-column scales: copy l_j = s_j v_j
         HIP_TRY(launch_scale_basis(sv->tb, sv->ka.L, sv->ka.ldl, sv->ka.scale, sv->op->n, kp1, dst_dev,
-                                   sv->op->ctx->stream));
-        HIP_TRY(hipStreamSynchronize(sv->op->ctx->stream));
+                                   sv->stream));
+        HIP_TRY(hipStreamSynchronize(sv->stream));
     } else if (which == 1) {
         if (!sv->rect) return fail(HK_EINVAL, "D exists for the generalized Hessenberg method only");
         HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->m, sv->ka.D, es * sv->ka.ldd, es * sv->op->m, kp1,
@@ -939,6 +986,13 @@ hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev)
     } else {
         return fail(HK_EINVAL, "which must be 0 (L), 1 (D) or 2 (stored L)");
     }
+    return HK_OK;
+}
+
+hk_status hk_solve_grid(const hk_solve* sv, int32_t* workgroups)
+{
+    if (!sv || !workgroups) return fail(HK_EINVAL, "null argument");
+    *workgroups = sv->G;
     return HK_OK;
 }
 
@@ -960,11 +1014,11 @@ hk_status hk_solve_timing_history(hk_solve* sv, int32_t max_runs, double* iterat
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (max_runs < 0 || !n) return fail(HK_EINVAL, "bad arguments");
-    const long long kept = std::min<long long>(sv->runs, hk_solve::NEV);
+    const long long kept = std::min<long long>(sv->runs, sv->nev);
     const int cnt = (int)std::min<long long>(kept, max_runs);
     for (int i = 0; i < cnt; ++i) {
         const long long run = sv->runs - cnt + i;
-        const int slot = (int)(run % hk_solve::NEV);
+        const int slot = (int)(run % sv->nev);
         float a = 0.f, b = 0.f;
         HIP_TRY(hipEventElapsedTime(&a, sv->ev[slot][0], sv->ev[slot][1]));
         HIP_TRY(hipEventElapsedTime(&b, sv->ev[slot][0], sv->ev[slot][2]));
@@ -1000,8 +1054,284 @@ hk_status hk_solve_destroy(hk_solve* sv)
     for (int i = 0; i < hk_solve::NEV; ++i)
         for (int q = 0; q < 3; ++q)
             if (sv->ev[i][q]) hipEventDestroy(sv->ev[i][q]);
-    hipFree(sv->ws);
+    if (sv->own_ws) hipFree(sv->ws);
     delete sv;
+    return HK_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== serving
+// Continuous batching on one device.  Requests are queued on arrival and
+// admitted in arrival order whenever a slot, the workspace they need within
+// the device-memory budget and the compute units of their basis kernel are
+// free.  Each admitted solve runs on its slot's stream with an ordinary
+// (non-cooperative) launch, so the basis kernels of up to `slots` requests
+// run side by side; the sum of their grids never exceeds the compute units
+// given to the server, which keeps every grid co-resident.  Retired
+// workspaces are pooled for reuse instead of freed, because freeing device
+// memory would wait for the solves still running.
+struct hk_server {
+    hk_context* ctx = nullptr;
+    size_t budget = 0;              // device bytes of workspace the server may hold
+    size_t held = 0;                // allocated (in use or pooled)
+    int wg_total = 0, wg_used = 0;  // compute units for basis kernels
+    struct Slot {
+        hipStream_t st = nullptr;
+        hk_solve* sv = nullptr;
+        int64_t ticket = -1;
+        void* buf = nullptr;
+        size_t cap = 0;
+    };
+    std::vector<Slot> slots;
+    struct Req {
+        int64_t ticket;
+        hk_op* op;
+        hk_params p;
+        const void* b;
+        void* x;
+    };
+    std::deque<Req> queue;
+    struct Res {
+        hk_status status = HK_OK;
+        int k_done = 0, grid = 0;
+        double t_submit = 0.0, t_start = 0.0, t_finish = 0.0;
+        bool done = false;
+    };
+    std::vector<Res> res;
+    std::vector<std::pair<void*, size_t>> pool;   // idle workspaces
+    int64_t completed = 0;
+    int running = 0;
+};
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void finish_request(hk_server* s, int64_t t, hk_status st, int k_done)
+{
+    auto& r = s->res[(size_t)t];
+    r.status = st;
+    r.k_done = k_done;
+    r.t_finish = now_s();
+    if (r.t_start == 0.0) r.t_start = r.t_finish;
+    r.done = true;
+    s->completed++;
+}
+
+// Retire finished solves, then admit queued requests while they fit.
+hk_status server_pump(hk_server* s)
+{
+    for (auto& sl : s->slots) {
+        if (!sl.sv) continue;
+        const hipError_t q = hipEventQuery(sl.sv->ev2);
+        if (q == hipErrorNotReady) continue;
+        const hk_status st = (q == hipSuccess) ? hk_solve_wait(sl.sv) : fail(HK_EDEVICE, "%s", hipGetErrorString(q));
+        finish_request(s, sl.ticket, st, sl.sv->k_done);
+        s->wg_used -= sl.sv->G;
+        s->running--;
+        hk_solve_destroy(sl.sv);           // the workspace is the server's
+        s->pool.emplace_back(sl.buf, sl.cap);
+        sl.sv = nullptr;
+        sl.ticket = -1;
+        sl.buf = nullptr;
+        sl.cap = 0;
+    }
+    while (!s->queue.empty()) {
+        hk_server::Slot* slot = nullptr;
+        for (auto& sl : s->slots)
+            if (!sl.sv) { slot = &sl; break; }
+        if (!slot) break;
+        const hk_server::Req rq = s->queue.front();
+        // grid: a fair share of the compute units, or as many as the
+        // problem needs when its tiles do not fit in a share
+        const int share = std::max(1, s->wg_total / (int)s->slots.size());
+        hk_params p = rq.p;
+        p.max_workgroups = rq.p.max_workgroups > 0 ? std::min(rq.p.max_workgroups, s->wg_total) : share;
+        hk_params pe{};
+        int rect = 0;
+        Plan pl;
+        size_t need = 0;
+        hk_status st = solve_plan(rq.op, &p, &pe, &rect, &pl, &need);
+        // a problem with more tiles than a share: the fewest extra shares
+        for (int cap = 2 * share; st == HK_EUNSUPPORTED && rq.p.max_workgroups == 0 && p.max_workgroups < s->wg_total;
+             cap += share) {
+            p.max_workgroups = std::min(cap, s->wg_total);
+            st = solve_plan(rq.op, &p, &pe, &rect, &pl, &need);
+        }
+        if (st < 0) {
+            s->queue.pop_front();
+            finish_request(s, rq.ticket, st, 0);
+            continue;
+        }
+        if (pl.G > s->wg_total - s->wg_used) break;          // wait for compute units
+        // workspace: the smallest pooled buffer that fits, else a new one
+        int pick = -1;
+        for (int i = 0; i < (int)s->pool.size(); ++i)
+            if (s->pool[i].second >= need && (pick < 0 || s->pool[i].second < s->pool[pick].second)) pick = i;
+        void* buf = nullptr;
+        size_t cap = 0;
+        if (pick >= 0) {
+            buf = s->pool[pick].first;
+            cap = s->pool[pick].second;
+            s->pool.erase(s->pool.begin() + pick);
+        } else {
+            if (s->held + need > s->budget && s->running == 0) {
+                // nothing runs: the idle buffers can be released cheaply
+                for (auto& b : s->pool) {
+                    hipFree(b.first);
+                    s->held -= b.second;
+                }
+                s->pool.clear();
+            }
+            if (s->held + need > s->budget) {
+                if (s->running > 0) break;                      // wait for memory
+                s->queue.pop_front();
+                finish_request(s, rq.ticket, fail(HK_ENOMEM, "workspace of %zu bytes exceeds the budget", need), 0);
+                continue;
+            }
+            if (hipMalloc(&buf, need) != hipSuccess) {
+                if (s->running > 0) break;
+                s->queue.pop_front();
+                finish_request(s, rq.ticket, fail(HK_ENOMEM, "hipMalloc of %zu bytes failed", need), 0);
+                continue;
+            }
+            cap = need;
+            s->held += need;
+        }
+        hk_solve* sv = nullptr;
+        st = solve_create(rq.op, &p, buf, cap, 1, slot->st, &sv);
+        if (st == HK_OK) {
+            st = hk_solve_run(sv, rq.b, rq.x);
+            if (st != HK_OK) {
+                hk_solve_destroy(sv);
+                sv = nullptr;
+            }
+        }
+        s->queue.pop_front();
+        if (st != HK_OK) {
+            s->pool.emplace_back(buf, cap);
+            finish_request(s, rq.ticket, st, 0);
+            continue;
+        }
+        slot->sv = sv;
+        slot->ticket = rq.ticket;
+        slot->buf = buf;
+        slot->cap = cap;
+        s->wg_used += sv->G;
+        s->running++;
+        auto& r = s->res[(size_t)rq.ticket];
+        r.t_start = now_s();
+        r.grid = sv->G;
+    }
+    return HK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hk_status hk_server_create(hk_context* ctx, int32_t slots, size_t budget_bytes, int32_t workgroups,
+                           hk_server** out)
+{
+    if (!ctx || !out) return fail(HK_EINVAL, "null argument");
+    *out = nullptr;
+    if (slots < 1 || slots > 16) return fail(HK_EINVAL, "slots = %d must be in [1, 16]", slots);
+    if (workgroups < 0) return fail(HK_EINVAL, "workgroups must be >= 0");
+    hk_status st = current_device(ctx);
+    if (st) return st;
+    auto* s = new (std::nothrow) hk_server;
+    if (!s) return fail(HK_ENOMEM, "host allocation failed");
+    s->ctx = ctx;
+    if (budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete s; return fail(HK_EDEVICE, "hipMemGetInfo failed"); }
+        budget_bytes = fr / 10 * 8;
+    }
+    s->budget = budget_bytes;
+    // a few compute units stay free for the short kernels of finishing solves
+    s->wg_total = workgroups > 0 ? std::min(workgroups, ctx->ncu) : std::max(1, ctx->ncu - 8);
+    s->slots.resize((size_t)slots);
+    for (auto& sl : s->slots)
+        if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess) {
+            hk_server_destroy(s);
+            return fail(HK_EDEVICE, "hipStreamCreateWithFlags failed");
+        }
+    *out = s;
+    return HK_OK;
+}
+
+hk_status hk_server_destroy(hk_server* s)
+{
+    if (!s) return fail(HK_EINVAL, "null server");
+    hipSetDevice(s->ctx->device);
+    for (auto& sl : s->slots) {
+        if (sl.st) hipStreamSynchronize(sl.st);
+        if (sl.sv) hk_solve_destroy(sl.sv);
+        if (sl.buf) hipFree(sl.buf);
+        if (sl.st) hipStreamDestroy(sl.st);
+    }
+    for (auto& b : s->pool) hipFree(b.first);
+    delete s;
+    return HK_OK;
+}
+
+hk_status hk_server_submit(hk_server* s, hk_op* op, const hk_params* params, const void* b_dev, void* x_dev,
+                           int64_t* ticket)
+{
+    if (!s || !op || !params || !b_dev || !x_dev || !ticket) return fail(HK_EINVAL, "null argument");
+    if (op->ctx->device != s->ctx->device) return fail(HK_EINVAL, "the operator lives on another device");
+    hk_status st = current_device(s->ctx);
+    if (st) return st;
+    const int64_t t = (int64_t)s->res.size();
+    s->res.emplace_back();
+    s->res.back().t_submit = now_s();
+    s->queue.push_back({t, op, *params, b_dev, x_dev});
+    *ticket = t;
+    return server_pump(s);
+}
+
+hk_status hk_server_poll(hk_server* s, int64_t* completed)
+{
+    if (!s) return fail(HK_EINVAL, "null server");
+    hk_status st = current_device(s->ctx);
+    if (st) return st;
+    st = server_pump(s);
+    if (completed) *completed = s->completed;
+    return st;
+}
+
+hk_status hk_server_wait(hk_server* s, int64_t ticket)
+{
+    if (!s || ticket < 0 || ticket >= (int64_t)s->res.size()) return fail(HK_EINVAL, "bad ticket");
+    hk_status st = current_device(s->ctx);
+    if (st) return st;
+    while (!s->res[(size_t)ticket].done) {
+        st = server_pump(s);
+        if (st) return st;
+        if (s->res[(size_t)ticket].done) break;
+        if (s->running == 0 && !s->queue.empty() && s->queue.front().ticket <= ticket)
+            return fail(HK_EDEVICE, "request %lld cannot be admitted", (long long)ticket);
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    return s->res[(size_t)ticket].status;
+}
+
+hk_status hk_server_result(hk_server* s, int64_t ticket, hk_status* status, int32_t* k_done, int32_t* workgroups,
+                           double* t_submit, double* t_start, double* t_finish)
+{
+    if (!s || ticket < 0 || ticket >= (int64_t)s->res.size()) return fail(HK_EINVAL, "bad ticket");
+    const auto& r = s->res[(size_t)ticket];
+    if (!r.done) return fail(HK_EINVAL, "request %lld has not finished", (long long)ticket);
+    if (status) *status = r.status;
+    if (k_done) *k_done = r.k_done;
+    if (workgroups) *workgroups = r.grid;
+    if (t_submit) *t_submit = r.t_submit;
+    if (t_start) *t_start = r.t_start;
+    if (t_finish) *t_finish = r.t_finish;
     return HK_OK;
 }
 

@@ -320,3 +320,61 @@ def config(name: str) -> Problem:
 
 
 CONFIG_NAMES = ("c1", "c1_tik", "c2", "c3")
+
+
+# --------------------------------------------------------------------------
+# serving mix
+# --------------------------------------------------------------------------
+SERVE_SEED = 0x5E7E
+# deblurring sizes the single-kernel tile plan accepts (n <= 256 tiles x 2048
+# pixels); the 1024 x 1024 images of the original mix exceed it
+SERVE_BLUR_SIZES = (128, 256, 384, 512)
+SERVE_TOMO_SIZES = (64, 128, 256)
+SERVE_TOMO_ANGLES = (60, 90, 120, 180)
+
+
+def serving_requests(n: int = 512, rate: float = 200.0, seed: int = SERVE_SEED):
+    """The serving mix: n requests with Poisson arrivals (exponential gaps of
+    mean 1/rate seconds), half deblurring (sizes SERVE_BLUR_SIZES, sigma
+    U[1, 6], r = round(4 sigma) - 1, boundary zero or reflective, sparse-sign
+    sketch with 8 nonzeros) and half tomography (SERVE_TOMO_SIZES x
+    SERVE_TOMO_ANGLES parallel-beam operators, Gaussian sketch); k uniform in
+    20..200, s = 2(k + 1), lambda in {0, 1e-3, 1e-2}.  Returns a list of
+    dicts with the arrival time (seconds from the first) and the request."""
+    rng = np.random.default_rng(seed)
+    t = np.concatenate([[0.0], np.cumsum(rng.exponential(1.0 / rate, size=n - 1))])
+    out = []
+    for i in range(n):
+        k = int(rng.integers(20, 201))
+        lam = float(rng.choice([0.0, 1e-3, 1e-2]))
+        req = {"arrival": float(t[i]), "k": k, "s": 2 * (k + 1), "lam": lam, "id": i}
+        if rng.random() < 0.5:
+            N = int(rng.choice(SERVE_BLUR_SIZES))
+            sigma = float(rng.uniform(1.0, 6.0))
+            req.update(kind="blur", N=N, sigma=sigma, r=radius_for_sigma(sigma),
+                       bc=int(rng.integers(0, 2)), sketch=SKETCH_SPARSE_SIGN, zeta=8)
+        else:
+            req.update(kind="csr", N=int(rng.choice(SERVE_TOMO_SIZES)),
+                       angles=int(rng.choice(SERVE_TOMO_ANGLES)), sketch=SKETCH_GAUSSIAN, zeta=8)
+        req["seed"] = SKETCH_SEED_BASE + 5000 + i
+        out.append(req)
+    return out
+
+
+def serving_data(req, phantom_seed: int = PHANTOM_SEED, noise_seed: int = NOISE_SEED):
+    """b (float64) of a serving request: a seeded phantom through the request's
+    operator plus 1% noise, applied with SciPy (blur) or a sparse product."""
+    rng = np.random.default_rng(phantom_seed + req["id"])
+    if req["kind"] == "blur":
+        N = req["N"]
+        x = phantom_piecewise(N, N, rng)
+        taps = gaussian_taps(req["sigma"], req["r"])
+        clean = blur_apply_scipy(x, taps, taps, req["bc"]).ravel()
+    else:
+        raise ValueError("tomography data needs its operator: use serving_tomo_data")
+    return add_noise(clean, 0.01, np.random.default_rng(noise_seed + req["id"]))
+
+
+def serving_tomo_data(req, A, phantom_seed: int = PHANTOM_SEED, noise_seed: int = NOISE_SEED):
+    x = phantom_ellipses(req["N"], np.random.default_rng(phantom_seed + req["id"])).ravel()
+    return add_noise(A @ x, 0.01, np.random.default_rng(noise_seed + req["id"]))
