@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhk.so")
 
-SOURCES = ["hk_iter_f64.hip", "hk_iter_f32.hip", "hk_iter_mix.hip", "hk_iter_h16.hip", "hk_kernels.hip", "hk_ls.hip",
+SOURCES = ["hk_iter_f64.hip", "hk_iter_f32.hip", "hk_iter_mix.hip", "hk_iter_h16.hip", "hk_bsk.hip", "hk_kernels.hip", "hk_ls.hip",
            "hk_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

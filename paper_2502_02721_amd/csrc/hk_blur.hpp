@@ -220,7 +220,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         {
             const int r0 = (int)(((long long)tile * a.s) / G), r1 = (int)(((long long)(tile + 1) * a.s) / G);
             const int nr = r1 - r0;
-            const int ntask = (j >= 1 && !a.nosk) ? nr * ((j == 1 ? 1 : 0) + 1 + (a.lam > 0.0 ? 1 : 0)) : 0;
+            const int ntask = (j >= 1 && a.stepsk) ? nr * ((j == 1 ? 1 : 0) + 1 + (a.lam > 0.0 ? 1 : 0)) : 0;
             const int wave = threadIdx.x >> 6;
             if (wave == 0) {
                 global_argmax_wave(a.amv + prv * G, a.ami + prv * G, 0, G, &s_amv, &s_ami);
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             // ---- 4. the tile: u = A l_j = s_j * blur(v_j), with the
             //         coefficient loads in flight; then the sketches of u
             //         and of v_j run on waves 1..7 while wave 0 forms h
-            const bool fsk = a.lam > 0.0 && !a.nosk;
+            const bool fsk = a.lam > 0.0 && a.stepsk;
             coef_loads([&]() {
                 mark(j, 12);
                 blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert,
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             __syncthreads();
             if (threadIdx.x < 64) {
                 coef_solve_wave();
-            } else if (!a.nosk) {
+            } else if (a.stepsk) {
                 // z_j partial = S2 u; f_j partial = S1 v_j (scaled by s_j when reduced)
                 sketch_rows_sum(wt, rows2, a.s, (double*)(a.zpart + par * GS + (long long)tile * a.s),
                                 (int)threadIdx.x - 64, NT - 64);
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             __syncthreads();
             mark(j, 15);
-            if (j == 0 && !a.nosk) {
+            if (j == 0 && a.stepsk) {
                 c_sketch();
                 sketch_rows_partial(wt, rows2, a.s, (double*)(a.cpart + (long long)tile * a.s));
             }
@@ -443,13 +443,13 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
             for (int e = threadIdx.x; e < TY * TX; e += NT) wt[e] *= sj;
             __syncthreads();
-            if (!a.nosk) sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart + par * GS, tile);   // z_j
+            if (a.stepsk) sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart + par * GS, tile);   // z_j
             mark(j, 15);
-            if (j == 0 && !a.nosk) {
+            if (j == 0 && a.stepsk) {
                 c_sketch();
                 sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
             }
-            if (a.lam > 0.0 && !a.nosk) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
+            if (a.lam > 0.0 && a.stepsk) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
                 for (int e = threadIdx.x; e < TY * TX; e += NT) {
                     const int yy = e / TX, xx = e - yy * TX;
                     wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];

@@ -1382,7 +1382,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
 
     // c partial = S2 b (scale from max|b| = |beta|)
     const double scc = fx_scale((double)a.m * fabs(beta) * 1.000001);
-    if (!a.nosk) {
+    if (a.stepsk) {
         for (int e = threadIdx.x; e < tm.E; e += NT) {
             int gi;
             wt[e] = elem_global(a.spm, tm, e, gi) ? (double)bvec[gi] : 0.0;
@@ -1410,7 +1410,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         ctl->beta = beta;
         if (rect) { a.gp[0] = g1; a.W[0] = alpha / beta; }
     }
-    if (a.lam > 0.0 && !a.nosk) {   // f_1 = S1 l_1
+    if (a.lam > 0.0 && a.stepsk) {   // f_1 = S1 l_1
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = threadIdx.x + i * NT;
@@ -1435,12 +1435,12 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
             if (rect) lds_append_row<TB>(PlL, a.k, (const TB*)a.PL, kp1, j);
         }
         op_forward(Lb + (long long)j * a.ldl);
-        if (j == 0 && !a.nosk) reduce_partials<SK>(a, a.cpart, inv_c, tile, a.c);
-        if (a.lam > 0.0 && !a.nosk) reduce_partials<SK>(a, a.fpart, inv_f, tile, a.F + (long long)j * a.s);
+        if (j == 0 && a.stepsk) reduce_partials<SK>(a, a.cpart, inv_c, tile, a.c);
+        if (a.lam > 0.0 && a.stepsk) reduce_partials<SK>(a, a.fpart, inv_f, tile, a.F + (long long)j * a.s);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
         for (int q = threadIdx.x; q < *pm.count; q += NT) pvD[pm.list_c[q]] = wt[pm.list_e[q]];
-        if (!a.nosk) sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart, tile);
+        if (a.stepsk) sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart, tile);
         if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
 
         // ---- phase B: coefficients and elimination against the data-space basis
@@ -1455,7 +1455,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         eliminate<TB, EPT>(acc, gm, Db, ldd, h_l, nh);
         zero_pivots<EPT>(acc, vm, pm.bits);
         tile_argmax<EPT>(acc, gm, vm, a.amv, a.ami, tile);
-        if (!a.nosk) reduce_partials<SK>(a, a.zpart, inv_z, tile, a.Z + (long long)j * a.s);
+        if (a.stepsk) reduce_partials<SK>(a, a.zpart, inv_z, tile, a.Z + (long long)j * a.s);
         if constexpr (SAMP) {
             __syncthreads();
             publish(acc, a.spm, tm, pm.bits, a.m, j + 1, 0);
@@ -1486,7 +1486,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         add_pivot<TB>(a.spm, tile, p, j + 1, pm, PD, kp1, Db, ldd);
 
         if (!rect) {
-            if (a.lam > 0.0 && j + 1 < a.k && !a.nosk) {
+            if (a.lam > 0.0 && j + 1 < a.k && a.stepsk) {
 #pragma unroll
                 for (int i = 0; i < EPT; ++i) {
                     const int e = threadIdx.x + i * NT;
@@ -1547,7 +1547,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         add_pivot<TB>(a.spn, tile, g, j + 1, pn, PL, kp1, Lb, a.ldl);
-        if (a.lam > 0.0 && !a.nosk) {
+        if (a.lam > 0.0 && a.stepsk) {
 #pragma unroll
             for (int i = 0; i < EPT; ++i) {
                 const int e = threadIdx.x + i * NT;

@@ -73,6 +73,7 @@ struct KArgs {
     int rect;                   // 1: generalized Hessenberg (sLSLU)
     int nosk;                   // 1: no sketches (the unsketched CMRH / LSLU projected problem)
     int coop;                   // 1: cooperative launch (whole-device grid)
+    int stepsk;                 // 1: sketch partials every step (0: none, or a block sketch at the end)
     int psamp, pnc;             // sampled pivoting: sample size (0: full argmax), Philox calls
     double* sval;               // published sample values, 4 x SAMPLE_SLOTS
     int* sidx;                  // their rows (-1: a pivot row), 4 x SAMPLE_SLOTS
@@ -171,6 +172,22 @@ hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KAr
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st);
 hipError_t launch_small_ls(const LsArgs& a, hipStream_t st);
 hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st);
+// block sketch C = S B with S generated (hk_bsk.hip)
+struct BskArgs {
+    const void* q;              // B: len x ncol, column-major, leading dimension ldq
+    long long ldq;
+    int len, ncol;
+    int s;                      // rows of S
+    int rt, ct, kc, chunk;      // row tiles, column tiles (64), contraction chunks and their length
+    uint32_t stream, k0, k1;    // Philox stream and key of S
+    double* part;               // rt * ct * kc tiles of 64 x 64
+    double* out;                // s x ncol, leading dimension ldo
+    int ldo;
+    double scale;               // 1 / sqrt(s)
+};
+hipError_t launch_block_sketch(int tq, int tg, const BskArgs& a, hipStream_t st);
+hipError_t launch_sketch_finish(const double* T, const double* T1, const double* H, const double* sc, int s, int k,
+                                double* Z, double* F, hipStream_t st);
 hipError_t launch_hess_rhs(double* F, double* c, int s, int k, double lam, const Ctl* ctl, hipStream_t st);
 hipError_t launch_apply(int dtype, int op, int ept, const ApplyArgs& a, hipStream_t st);
 hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double* scale, int64_t len,

@@ -94,6 +94,12 @@ struct hk_solve {
     hipEvent_t ev[NEV][3] = {};
     hipStream_t stream = nullptr;          // where runs are ordered
     bool own_ws = true;                    // the workspace was allocated here
+    // Gaussian sketches formed at the end as block contractions:
+    // T = S2 [basis of the data space], c = S2 b, T1 = S1 L_k, then Z, F
+    bool zend = false;
+    BskArgs bz{}, bc{}, bf{};
+    double* T = nullptr;
+    double* T1 = nullptr;
     long long runs = 0;                    // runs launched
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;   // of the last run
     bool ran = false;
@@ -346,6 +352,31 @@ int grid_cap(const hk_context* ctx, const hk_params* p)
     return p->max_workgroups > 0 ? std::min(ctx->ncu, p->max_workgroups) : ctx->ncu;
 }
 
+// Block sketch of `ncol` columns of length `len` by s rows: 64 x 64 output
+// tiles times chunks of the contraction, about 1024 workgroups in all.
+BskArgs bsk_plan(int64_t len, int ncol, int s)
+{
+    BskArgs b{};
+    b.len = (int)len;
+    b.ncol = ncol;
+    b.s = s;
+    b.rt = (s + 63) / 64;
+    b.ct = (ncol + 63) / 64;
+    const int64_t kc0 = std::max<int64_t>(1, (1024 + b.rt * b.ct - 1) / (b.rt * b.ct));
+    const int64_t per = (len + kc0 - 1) / kc0;
+    b.chunk = (int)std::max<int64_t>(16, (per + 15) / 16 * 16);
+    b.kc = (int)((len + b.chunk - 1) / b.chunk);
+    b.ldo = s;
+    b.scale = 1.0 / std::sqrt((double)s);
+    return b;
+}
+
+size_t bsk_tiles(int64_t len, int ncol, int s)
+{
+    const BskArgs b = bsk_plan(len, ncol, s);
+    return (size_t)b.rt * b.ct * b.kc;
+}
+
 // The parameters a solve runs with: without a sketch the small problem has
 // the k + 1 rows of H_{k+1,k}, so s = k + 1 (and no sparse-sign columns).
 hk_params effective_params(const hk_params& p)
@@ -360,7 +391,7 @@ hk_params effective_params(const hk_params& p)
 
 struct WsLayout {
     size_t ctl, L, D, H, W, tp, gp, PD, PL, pvD, pvL, amv, ami, zpart, fpart, cpart, Z, F, c;
-    size_t Q, R, r, y, res, d, trace, scale, wpart, sval, sidx, total;
+    size_t Q, R, r, y, res, d, trace, scale, wpart, sval, sidx, T, T1, part, total;
     int trace_cap;
     int64_t ldl, ldd;
 };
@@ -409,6 +440,13 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
     w.scale = take(sizeof(double) * kp1);
     w.wpart = take(sizeof(double) * 2 * (size_t)kp1 * std::max(1, nslot));
     w.sval = take(sizeof(double) * 4 * SAMPLE_SLOTS);
+    if (p->sketch == HK_SKETCH_GAUSSIAN && (p->basis_dtype == HK_F64 || p->basis_dtype == HK_F32)) {   // end-of-solve block sketches
+        w.T = take(sizeof(double) * (size_t)s * kp1);
+        w.T1 = take(sizeof(double) * (size_t)s * k);
+        const int64_t lz = rect ? op->m : op->n;
+        const size_t tiles = std::max(std::max(bsk_tiles(lz, kp1, s), bsk_tiles(op->m, 1, s)), bsk_tiles(op->n, k, s));
+        w.part = take(sizeof(double) * 4096 * tiles);
+    }
     w.sidx = take(sizeof(int) * 4 * SAMPLE_SLOTS);
     w.total = off;
     return w;
@@ -772,6 +810,11 @@ static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t
     a.rect = rect;
     a.nosk = (p->sketch == HK_SKETCH_NONE) ? 1 : 0;
     a.coop = p->max_workgroups > 0 ? 0 : 1;
+    // The block sketch reads Z through the Hessenberg relation A L_k =
+    // L_{k+1} H, which a stored basis satisfies to its rounding: FP64 and
+    // FP32 bases use it; 16-bit bases keep the exact per-step z_j = S2 A l_j.
+    sv->zend = (p->sketch == HK_SKETCH_GAUSSIAN) && (p->basis_dtype == HK_F64 || p->basis_dtype == HK_F32);
+    a.stepsk = (p->sketch == HK_SKETCH_NONE || sv->zend) ? 0 : 1;
     a.psamp = p->pivot_sample;
     a.pnc = (p->pivot_sample + 3) / 4 + 2;
     a.sval = (double*)(base + w.sval);
@@ -814,6 +857,32 @@ static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t
     a.spx = pl.spx;
     a.trace_cap = w.trace_cap;
     a.trace = w.trace_cap ? (unsigned long long*)(base + w.trace) : nullptr;
+    if (sv->zend) {
+        const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
+        sv->T = (double*)(base + w.T);
+        sv->T1 = (double*)(base + w.T1);
+        double* part = (double*)(base + w.part);
+        // T = S2 [d_1 .. d_{k+1}] (the data-space basis)
+        sv->bz = bsk_plan(rect ? op->m : op->n, p->k + 1, p->s);
+        sv->bz.q = rect ? a.D : a.L;
+        sv->bz.ldq = rect ? a.ldd : a.ldl;
+        sv->bz.stream = 2u; sv->bz.k0 = k0; sv->bz.k1 = k1;
+        sv->bz.part = part;
+        sv->bz.out = sv->T;
+        // c = S2 b (b is set per run)
+        sv->bc = bsk_plan(op->m, 1, p->s);
+        sv->bc.ldq = op->m;
+        sv->bc.stream = 2u; sv->bc.k0 = k0; sv->bc.k1 = k1;
+        sv->bc.part = part;
+        sv->bc.out = a.c;
+        // T1 = S1 [l_1 .. l_k]
+        sv->bf = bsk_plan(op->n, p->k, p->s);
+        sv->bf.q = a.L;
+        sv->bf.ldq = a.ldl;
+        sv->bf.stream = 1u; sv->bf.k0 = k0; sv->bf.k1 = k1;
+        sv->bf.part = part;
+        sv->bf.out = sv->T1;
+    }
     LsArgs& l = sv->la;
     l.s = p->s; l.k = p->k; l.lam = p->lambda;
     // unsketched: Z is H_{k+1,k} itself (column-major, leading dimension
@@ -864,6 +933,20 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
     HIP_TRY(launch_iterate(sv->tb, sv->op->dtype, sv->kernel, sv->sk, sv->ept, a, s));
     HIP_TRY(hipEventRecord(sv->ev1, s));
     if (a.nosk) HIP_TRY(launch_hess_rhs(a.F, a.c, sv->prm.s, sv->prm.k, sv->prm.lambda, a.ctl, s));
+    if (sv->zend) {
+        // Gaussian sketches of the whole basis: Z = (S2 D_{k+1}) H_{k+1,k},
+        // F = S1 L_k, c = S2 b (the Gaussian entries in the data's precision)
+        const int tg = sv->op->dtype == HK_F64 ? 0 : 1;
+        const bool fz = sv->prm.lambda > 0.0;
+        HIP_TRY(launch_block_sketch(sv->tb, tg, sv->bz, s));
+        BskArgs bc = sv->bc;
+        bc.q = b_dev;
+        HIP_TRY(launch_block_sketch(sv->op->dtype == HK_F64 ? 0 : 1, tg, bc, s));
+        if (fz) HIP_TRY(launch_block_sketch(sv->tb, tg, sv->bf, s));
+        HIP_TRY(launch_sketch_finish(sv->T, fz ? sv->T1 : nullptr, a.H,
+                                     sv->kernel == OP_BLUR_ONEBAR ? a.scale : nullptr, sv->prm.s, sv->prm.k, a.Z,
+                                     a.F, s));
+    }
     HIP_TRY(launch_small_ls(sv->la, s));
     CombineArgs c = sv->ca;
     c.x = x_dev;
