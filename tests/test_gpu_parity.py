@@ -199,6 +199,49 @@ def test_k_equals_n_exact_solve(hk, ctx):
     assert rel(g["x"], np.linalg.solve(A, b)) <= 1e-10
 
 
+@pytest.mark.parametrize("dtype,k", [("f32", 255), ("f64", 180)])
+def test_largest_k(hk, ctx, orc, dtype, k):
+    # k = 255, the largest basis the kernels hold (k + 1 pivot slots); the
+    # pivot block (k (k + 1) / 2 entries) lives in LDS, which bounds k at
+    # about 180 for FP64 bases.  A random sparse matrix keeps the long basis
+    # well conditioned: on a 64 x 64 blur the FP64 oracle's own pivots split
+    # at step 77 under one-ulp changes of b, so no bar would hold there.
+    P = random_csr(1200, 1200, 0.02, k=k, s=2 * (k + 1), lam=1e-3, dtype=dtype)
+    _parity(hk, ctx, orc, P, method=hk.HK_METHOD_HESSENBERG)
+
+
+def test_k_beyond_lds_refused(hk, ctx):
+    P = tiny_blur(64, 64, 2.0, 7, W.BC_ZERO, k=255, s=512, dtype="f64")
+    from hk_gpu import make_operator
+    op = make_operator(hk, ctx, P)
+    with pytest.raises(hk.HKError) as e:
+        hk.Solve(op, k=255, s=512)
+    assert e.value.status == hk.HK_EUNSUPPORTED
+
+
+def test_largest_image(hk, ctx, orc):
+    # n = 524288 = 256 tiles of 2048 pixels, the largest single-kernel plan
+    P = tiny_blur(1024, 512, 2.0, 7, W.BC_REFLECT, k=12, s=48, lam=1e-2, sketch=W.SKETCH_SPARSE_SIGN,
+                  zeta=8, dtype="f32")
+    _parity(hk, ctx, orc, P)
+
+
+def test_large_sketch_column_ls(hk, ctx, orc):
+    # s = 8192: the blocked least-squares panel does not fit in LDS, so the
+    # column-by-column kernel solves the small problem
+    P = tiny_blur(64, 64, 2.0, 7, W.BC_ZERO, k=12, s=8192, lam=0.0, sketch=W.SKETCH_GAUSSIAN, dtype="f64")
+    _parity(hk, ctx, orc, P)
+
+
+def test_image_too_large_refused(hk, ctx):
+    P = tiny_blur(1024, 1024, 2.0, 7, W.BC_ZERO, k=4, s=10, dtype="f32")
+    from hk_gpu import make_operator
+    op = make_operator(hk, ctx, P)
+    with pytest.raises(hk.HKError) as e:
+        hk.Solve(op, k=4, s=10)
+    assert e.value.status == hk.HK_EUNSUPPORTED
+
+
 def test_repeat_runs_are_bitwise_identical(hk, ctx):
     P = tiny_blur(64, 96, 2.0, 7, W.BC_REFLECT, k=30, s=62, lam=1e-3, sketch=W.SKETCH_SPARSE_SIGN,
                   dtype="f32")
