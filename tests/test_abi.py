@@ -45,6 +45,14 @@ def test_version_and_null_argument_errors(hk):
     assert L.hk_context_create(0, None, None) == hk.HK_EINVAL
     assert L.hk_op_create_blur(None, 4, 4, None, None, 1, 0, 0, None) == hk.HK_EINVAL
     assert L.hk_solve_create(None, None, None) == hk.HK_EINVAL
+    assert L.hk_solve_grid(None, None) == hk.HK_EINVAL
+    # the serving loop: null handles are refused before any device work
+    assert L.hk_server_create(None, 4, 0, 0, None) == hk.HK_EINVAL
+    assert L.hk_server_destroy(None) == hk.HK_EINVAL
+    assert L.hk_server_submit(None, None, None, None, None, None) == hk.HK_EINVAL
+    assert L.hk_server_poll(None, None) == hk.HK_EINVAL
+    assert L.hk_server_wait(None, 0) == hk.HK_EINVAL
+    assert L.hk_server_result(None, 0, None, None, None, None, None, None) == hk.HK_EINVAL
 
 
 def test_params_struct_layout(hk, tmp_path):
