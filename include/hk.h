@@ -53,7 +53,7 @@ enum {
     HK_ENOMEM = -2,        /* device or host allocation failed */
     HK_EDEVICE = -3,       /* HIP runtime error or device-side abort */
     HK_ENUMERIC = -4,      /* NaN/Inf in the data, or a rank-deficient sketched problem */
-    HK_EUNSUPPORTED = -5   /* valid request outside what this build implements */
+    HK_EUNSUPPORTED = -5   /* valid request outside what this library implements */
 };
 
 typedef int32_t hk_dtype;
@@ -254,7 +254,7 @@ hk_status hk_solve_get_trace(hk_solve* sv, int32_t max, uint64_t* ticks, int32_t
 hk_status hk_solve_destroy(hk_solve* sv);
 
 /* ---------------------------------------------------------------- serving
- * Continuous batching of solves on one device (the benchmark spec's serving
+ * Continuous batching of solves on one device (a serving
  * loop).  Requests are queued on arrival and admitted in arrival order as
  * soon as a slot is free, the workspace they need fits in the device-memory
  * budget and the compute units their basis kernel takes are free; admitted
