@@ -23,8 +23,18 @@ constexpr int LSB_NT = 512;
 constexpr int LSB_NW = LSB_NT / 64;
 constexpr int PNB = 16;                            // panel width (the MFMA tile)
 constexpr double CHOL_TINY = 1e-12;                // smallest accepted scaled pivot
+constexpr int PD = 4;                              // pipelined steps (4 MFMA K steps each) in flight
+constexpr int TNK = 16;                            // K steps per batch of the Q^T P product
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+
+// Column stride of the LDS panel: R rounded up to 4 mod 32 doubles, so the 16
+// columns x 4 rows that one MFMA operand load touches fall in different banks
+// (a stride that is a multiple of 32 doubles puts all 16 columns in one bank).
+__device__ __host__ __forceinline__ int panel_ld(int R)
+{
+    return R + ((4 - R) & 31);
+}
 
 // v_mfma_f64_16x16x4f64 operand layout: lane l holds A(l % 16, l / 16) and
 // B(l / 16, l % 16); element v of the accumulator is D(l / 16 + 4 v, l % 16)
@@ -69,113 +79,133 @@ __device__ __forceinline__ double block_sum1(double v, double* red)
     return t;
 }
 
-// W[c * 16 + p] = sum_i Q[i * QS + c] P[p * R + i] for c < j0 (MFMA: A = Q^T
+// W[c * 16 + p] = sum_i Q[i * QS + c] P[p * RP + i] for c < j0 (MFMA: A = Q^T
 // block, B = P block, K = rows).  Work units: ncb column blocks x nsplit row
-// groups (at most 8 units at a time, one per wave); row-group partials are
-// summed through red (at most 8 x 256 doubles).
+// groups, unit u on wave u % 8; row-group partials are summed through red (at
+// most 8 x 256 doubles, nsplit > 1 only when ncb * nsplit <= 8).  A unit
+// takes its rows in batches of TNK MFMA K steps (4 rows each) whose loads are
+// all issued before the first product; rows past the unit's end are read at
+// a clamped address and contribute exact zeros.
 __device__ void proj_tn(const double* __restrict__ Q, int QS, int R, int j0, const double* P, double* W, double* red)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // wave-uniform loop control (scalar branches)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ncb = (j0 + 15) >> 4;
     const int nsplit = max(1, LSB_NW / ncb);
     const int rows_per = (((R + nsplit - 1) / nsplit) + 3) & ~3;
     const int li = lane & 15, lk = lane >> 4;
-    for (int u0 = 0; u0 < ncb * nsplit; u0 += LSB_NW) {
-        const int u = u0 + wave;
-        const bool active = u < ncb * nsplit;
-        const int cb = active ? u / nsplit : 0, g = active ? u - cb * nsplit : 0;
+    const int nun = ncb * nsplit;
+    const int nu = wave < nun ? (nun - 1 - wave) / LSB_NW + 1 : 0;   // units of this wave
+    // rows of a unit: [g rows_per, min(R, (g + 1) rows_per)); with nsplit > 1
+    // the wave holds one unit (g = wave % nsplit), otherwise every unit has all R
+    const int gw = nsplit > 1 ? wave % nsplit : 0;
+    const int r0 = gw * rows_per, r1 = min(R, r0 + rows_per);
+    for (int q = 0; q < nu; ++q) {
+        const int u = wave + LSB_NW * q;
+        const int cb = u / nsplit;
         const int c = cb * 16 + li;
-        const bool cok = active && c < j0;
-        const double* qc = Q + min(c, j0 - 1);    // row-major Q: qc[row * QS]
-        const double* pc = P + li * R;
-        const int r0 = g * rows_per, r1 = active ? min(R, r0 + rows_per) : r0;
+        const bool cok = c < j0;
+        const double* qc = Q + min(c, j0 - 1);
+        const double* pc = P + li * panel_ld(R);
         d4v d = {0.0, 0.0, 0.0, 0.0};
-        int i0 = r0;
-        for (; i0 + 16 <= r1; i0 += 16) {          // four K steps in flight
-            double qa[4], pb[4];
+        for (int i0 = r0; i0 < r1; i0 += 4 * TNK) {
+            double qa[TNK], pb[TNK];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int row = i0 + 4 * t + lk;
+            for (int t = 0; t < TNK; ++t) {
+                const int row = min(i0 + 4 * t + lk, R - 1);
                 qa[t] = qc[(long long)row * QS];
                 pb[t] = pc[row];
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) d = mfma16(cok ? qa[t] : 0.0, pb[t], d);
-        }
-        for (; i0 < r1; i0 += 4) {
-            const int row = i0 + lk;
-            const bool rok = row < r1;
-            const double qa = qc[(long long)min(row, R - 1) * QS];
-            const double pb = pc[min(row, R - 1)];
-            d = mfma16((cok && rok) ? qa : 0.0, rok ? pb : 0.0, d);
+            for (int t = 0; t < TNK; ++t) {
+                const bool rok = i0 + 4 * t + lk < r1;
+                d = mfma16((cok && rok) ? qa[t] : 0.0, rok ? pb[t] : 0.0, d);
+            }
         }
         if (nsplit == 1) {
-            if (active) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int cr = cb * 16 + lk + 4 * v;
-                    if (cr < j0) W[cr * PNB + li] = d[v];
-                }
+            for (int v = 0; v < 4; ++v) {
+                const int cr = cb * 16 + lk + 4 * v;
+                if (cr < j0) W[cr * PNB + li] = d[v];
             }
         } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) red[wave * 256 + (lk + 4 * v) * 16 + li] = active ? d[v] : 0.0;
+            for (int v = 0; v < 4; ++v) red[wave * 256 + (lk + 4 * v) * 16 + li] = d[v];
         }
     }
     if (nsplit > 1) {
         __syncthreads();
-        // ncb * nsplit <= LSB_NW here: unit u = cb * nsplit + g sits in red[u]
+        // unit u = cb * nsplit + g (on wave u) sits in red[u]
         for (int e = threadIdx.x; e < ncb * 256; e += LSB_NT) {
             const int cb = e >> 8, ij = e & 255;
             const int cr = cb * 16 + (ij >> 4);
             double t = 0.0;
-            for (int g = 0; g < nsplit; ++g) t += red[(cb * nsplit + g) * 256 + ij];
+            for (int g = 0; g < nsplit; ++g) t += (g * rows_per < R) ? red[(cb * nsplit + g) * 256 + ij] : 0.0;
             if (cr < j0) W[cr * PNB + (ij & 15)] = t;
         }
     }
     __syncthreads();
 }
 
-// P[p * R + i] -= sum_{c < j0} Q[i * QS + c] W[c * 16 + p] (MFMA: D = P block of
-// 16 rows, A = Q block, B = W block, K = Q columns).
+// P[p * RP + i] -= sum_{c < j0} Q[i * QS + c] W[c * 16 + p] (MFMA: D = P block of
+// 16 rows, A = Q block, B = W block, K = Q columns).  j0 is a panel start, a
+// multiple of 16.  A wave's (row block, 16-column chunk) steps form one
+// software pipeline with the loads of the next PD steps in flight; each row
+// block takes the columns in increasing order.
 __device__ void proj_update(const double* __restrict__ Q, int QS, int R, int j0, double* P, const double* W)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lk = lane >> 4;
     const int nrb = (R + 15) >> 4;
-    for (int rb = wave; rb < nrb; rb += LSB_NW) {
-        const int rA = rb * 16 + li;               // row of the A operand
-        const bool rAok = rA < R;
-        const double* qrow = Q + (long long)min(rA, R - 1) * QS;   // row-major Q
-        d4v d;
+    const int nch = j0 >> 4;
+    const int RP = panel_ld(R);
+    const int nrw = wave < nrb ? (nrb - 1 - wave) / LSB_NW + 1 : 0;   // row blocks of this wave
+    const int nit = nrw * nch;
+    if (nit == 0) return;
+    double qa[PD][4], wb[PD][4];
+    int iq = 0, ic = 0;                            // row block and chunk of the next issue
+    auto issue = [&](double (&q)[4], double (&w)[4]) {
+        const int rb = wave + LSB_NW * min(iq, nrw - 1);
+        const double* qrow = Q + (long long)min(rb * 16 + li, R - 1) * QS + 16 * ic;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = rb * 16 + lk + 4 * v;
-            d[v] = row < R ? P[li * R + row] : 0.0;
+        for (int t = 0; t < 4; ++t) {
+            q[t] = qrow[4 * t + lk];
+            w[t] = W[(16 * ic + 4 * t + lk) * PNB + li];
         }
-        int c = 0;
-        for (; c + 16 <= j0; c += 16) {            // four K steps in flight
-            double qa[4], wb[4];
+        if (++ic == nch) { ic = 0; ++iq; }
+    };
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int cc = c + 4 * t + lk;
-                qa[t] = qrow[cc];
-                wb[t] = W[cc * PNB + li];
+    for (int sl = 0; sl < PD; ++sl) issue(qa[sl], wb[sl]);
+    int cq = 0, cc = 0;                            // row block and chunk being consumed
+    d4v d;
+    for (int it0 = 0; it0 < nit; it0 += PD) {
+#pragma unroll
+        for (int sl = 0; sl < PD; ++sl) {
+            if (it0 + sl < nit) {
+                const int rb = wave + LSB_NW * cq;
+                const bool rAok = rb * 16 + li < R;
+                if (cc == 0) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = rb * 16 + lk + 4 * v;
+                        d[v] = row < R ? P[li * RP + row] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) d = mfma16(rAok ? -qa[sl][t] : 0.0, wb[sl][t], d);
+                if (cc == nch - 1) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = rb * 16 + lk + 4 * v;
+                        if (row < R) P[li * RP + row] = d[v];
+                    }
+                    cc = 0;
+                    ++cq;
+                } else {
+                    ++cc;
+                }
             }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) d = mfma16(rAok ? -qa[t] : 0.0, wb[t], d);
-        }
-        for (; c < j0; c += 4) {
-            const int cc = c + lk;
-            const bool ok = cc < j0;
-            const double qa = qrow[min(cc, j0 - 1)];
-            const double wb = W[min(cc, j0 - 1) * PNB + li];
-            d = mfma16((ok && rAok) ? -qa : 0.0, ok ? wb : 0.0, d);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = rb * 16 + lk + 4 * v;
-            if (row < R) P[li * R + row] = d[v];
+            issue(qa[sl], wb[sl]);                 // unconditional (clamped past the end)
         }
     }
 }
@@ -188,9 +218,17 @@ __device__ void panel_gram(const double* P, int R, double* G, double* red)
     const int li = lane & 15, lk = lane >> 4;
     const int slice = (((R + LSB_NW - 1) / LSB_NW) + 3) & ~3;
     const int r0 = wave * slice, r1 = min(R, r0 + slice);
-    const double* pc = P + li * R;
+    const double* pc = P + li * panel_ld(R);
     d4v d = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = r0; i0 < r1; i0 += 4) {
+    int i0 = r0;
+    for (; i0 + 16 <= r1; i0 += 16) {              // four K steps' loads first
+        double x[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = pc[i0 + 4 * t + lk];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) d = mfma16(x[t], x[t], d);
+    }
+    for (; i0 < r1; i0 += 4) {
         const int row = i0 + lk;
         const double x = row < r1 ? pc[row] : 0.0;
         d = mfma16(x, x, d);
@@ -207,62 +245,113 @@ __device__ void panel_gram(const double* P, int R, double* G, double* red)
     __syncthreads();
 }
 
+// Timestamp of a traced run (tr null otherwise).
+__device__ __forceinline__ void lsmark(unsigned long long* tr, int slot)
+{
+    if (tr && threadIdx.x == 0) tr[slot] = wall_clock64();
+}
+
+// Right-looking Cholesky of the nb x nb leading block, row i of the matrix in
+// the registers of lane i (lanes 16..63 and rows >= nb hold zeros); column c
+// is broadcast by readlane, so a step costs no LDS round trip.  Same
+// operations, same order as the textbook right-looking loop.  FULL: nb == 16
+// at compile time.  Returns false at a pivot below CHOL_TINY or not finite.
+template <bool FULL>
+__device__ __forceinline__ bool chol_rows(double (&r)[PNB], int lane, int nb_)
+{
+    const int nbc = FULL ? PNB : nb_;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < PNB; ++c) {
+        if (c < nbc && ok) {                    // uniform over the wave
+            const double piv = readlane_d(r[c], c);
+            if (!(piv > CHOL_TINY) || !isfinite(piv)) {
+                ok = false;
+            } else {
+                const double lc = sqrt(piv);
+                if (lane == c) r[c] = lc;
+                else if (lane > c && lane < nbc) r[c] = r[c] / lc;
+#pragma unroll
+                for (int j = c + 1; j < PNB; ++j) {
+                    if (j < nbc) {
+                        const double ljc = readlane_d(r[c], j);
+                        if (lane >= j && lane < nbc) r[j] = fma(-r[c], ljc, r[j]);
+                    }
+                }
+            }
+        }
+    }
+    return ok;
+}
+
 // One CholeskyQR stage on the nb leading panel columns:
 //   G = P^T P, s = sqrt(diag G) (scale = true) or 1, S^-1 G S^-1 = L L^T,
 //   P <- P S^-1 L^-T, and the stage's factor Rs = L^T S (upper) replaces
 //   rcur by Rs rcur.  Returns false (P untouched) when a pivot of the scaled
 //   Gram matrix is below CHOL_TINY.  G, Lm, rcur, rtmp: 256 doubles each.
 __device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, double* Lm, double* sc,
-                             double* rcur, double* rtmp, double* red, int* s_ok)
+                             double* rcur, double* rtmp, double* red, int* s_ok, unsigned long long* tr)
 {
     panel_gram(P, R, G, red);
+    lsmark(tr, 0);
+    const int RP = panel_ld(R);
     if (threadIdx.x < 64) {
+        // Cholesky of the scaled Gram matrix, row i in the registers of lane i
         const int lane = threadIdx.x;
-        if (lane < PNB) sc[lane] = (lane < nb) ? (scale ? sqrt(G[lane * 16 + lane]) : 1.0) : 1.0;
-        __builtin_amdgcn_wave_barrier();
-        bool ok = true;
-        for (int q = lane; q < 256; q += 64) {
-            const int i = q >> 4, j = q & 15;
-            Lm[q] = (i < nb && j < nb) ? G[q] / (sc[i] * sc[j]) : 0.0;
+        const double sl = (lane < nb && scale) ? sqrt(G[(lane & 15) * 16 + (lane & 15)]) : 1.0;
+        if (lane < PNB) sc[lane] = sl;
+        double r[PNB];
+#pragma unroll
+        for (int j = 0; j < PNB; ++j) {
+            const double sj = readlane_d(sl, j);
+            r[j] = (lane < nb && j < nb) ? G[(lane & 15) * 16 + j] / (sl * sj) : 0.0;
         }
-        __builtin_amdgcn_wave_barrier();
-        for (int c = 0; c < nb; ++c) {             // right-looking Cholesky, lower triangle
-            const double piv = Lm[c * 16 + c];
-            if (!(piv > CHOL_TINY) || !isfinite(piv)) { ok = false; break; }
-            const double lc = sqrt(piv);
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) Lm[c * 16 + c] = lc;
-            if (lane > c && lane < nb) Lm[lane * 16 + c] = Lm[lane * 16 + c] / lc;
-            __builtin_amdgcn_wave_barrier();
-            for (int q = lane; q < 256; q += 64) {
-                const int i = q >> 4, j = q & 15;
-                if (j > c && i >= j && i < nb) Lm[q] = fma(-Lm[i * 16 + c], Lm[j * 16 + c], Lm[q]);
-            }
-            __builtin_amdgcn_wave_barrier();
+        const bool ok = (nb == PNB) ? chol_rows<true>(r, lane, nb) : chol_rows<false>(r, lane, nb);
+        double dg = 1.0;
+#pragma unroll
+        for (int j = 0; j < PNB; ++j) if (j == lane) dg = r[j];
+        if (lane < PNB) {
+#pragma unroll
+            for (int j = 0; j < PNB; ++j) Lm[lane * 16 + j] = r[j];
         }
         if (lane == 0) *s_ok = ok ? 1 : 0;
         // reciprocals of the scales and of L's diagonal for the row solve
         if (ok && lane < PNB) {
-            rtmp[lane] = (lane < nb) ? 1.0 / sc[lane] : 0.0;
-            rtmp[16 + lane] = (lane < nb) ? 1.0 / Lm[lane * 16 + lane] : 0.0;
+            rtmp[lane] = (lane < nb) ? 1.0 / sl : 0.0;
+            rtmp[16 + lane] = (lane < nb) ? 1.0 / dg : 0.0;
         }
     }
     __syncthreads();
+    lsmark(tr, 1);
     if (!*s_ok) return false;
-    // rows: y L^T = x S^-1, forward over the columns
-    for (int i = threadIdx.x; i < R; i += LSB_NT) {
-        double y[PNB];
+    // rows: y L^T = x S^-1, forward over the columns; a thread takes rows i
+    // and i + LSB_NT together, two independent chains
+    for (int i = threadIdx.x; i < R; i += 2 * LSB_NT) {
+        const int i2 = min(i + LSB_NT, R - 1);
+        const bool two = i + LSB_NT < R;
+        double y[PNB], z[PNB];
 #pragma unroll
         for (int j = 0; j < PNB; ++j) {
-            double t = (j < nb) ? P[j * R + i] * rtmp[j] : 0.0;
+            double t = (j < nb) ? P[j * RP + i] * rtmp[j] : 0.0;
+            double u = (j < nb) ? P[j * RP + i2] * rtmp[j] : 0.0;
 #pragma unroll
-            for (int q = 0; q < j; ++q) t = fma(-y[q], Lm[j * 16 + q], t);
+            for (int q = 0; q < j; ++q) {
+                const double l = Lm[j * 16 + q];
+                t = fma(-y[q], l, t);
+                u = fma(-z[q], l, u);
+            }
             y[j] = (j < nb) ? t * rtmp[16 + j] : 0.0;
+            z[j] = (j < nb) ? u * rtmp[16 + j] : 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < PNB; ++j)
-            if (j < nb) P[j * R + i] = y[j];
+        for (int j = 0; j < PNB; ++j) {
+            if (j < nb) {
+                P[j * RP + i] = y[j];
+                if (two) P[j * RP + i2] = z[j];
+            }
+        }
     }
+    lsmark(tr, 2);
     // rcur <- (L^T S) rcur (G is free once the Cholesky factor is in Lm)
     if (threadIdx.x < 256) {
         const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
@@ -274,6 +363,7 @@ __device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, do
     __syncthreads();
     if (threadIdx.x < 256) rcur[threadIdx.x] = G[threadIdx.x];
     __syncthreads();
+    lsmark(tr, 3);
     return true;
 }
 
@@ -294,8 +384,9 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
     const int s = a.s, k = a.k;
     const int R = a.lam > 0.0 ? 2 * s : s;
     const int ncol = kd + 1;                       // basis columns + right-hand side
-    double* P = (double*)smem;                     // NB x R panel, column-major
-    double* W = P + (size_t)NB * R;                // (k + 1) x NB projections
+    const int RP = panel_ld(R);
+    double* P = (double*)smem;                     // NB x R panel, column-major, column stride RP
+    double* W = P + (size_t)NB * RP;               // (k + 1) x NB projections
     double* red = W + (size_t)(k + 1) * NB;        // LSB_NW x 256
     double* racc = red + LSB_NW * 256;             // (k + 1) x NB: R(0 .. col, col) of the panel (d for column kd)
     double* G = racc + (size_t)(k + 1) * NB;       // 256
@@ -317,28 +408,33 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
     for (int j0 = 0; j0 < ncol; j0 += NB) {
         const int nb = min(NB, ncol - j0);
         // ---- panel: M(:, j0 .. j0 + nb) (column kd is [c; 0]); unused columns 0.
-        // Eight loads in flight per thread (clamped addresses, masked values).
-        for (int e0 = 0; e0 < NB * R; e0 += 8 * LSB_NT) {
-            double v[8];
+        // A thread takes rows i and i + LSB_NT of all 16 columns: 32 loads in
+        // flight (clamped addresses, masked values), no index division.
+        for (int ib = 0; ib < R; ib += 2 * LSB_NT) {
+            double v[2][NB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = min(e0 + u * LSB_NT + (int)threadIdx.x, NB * R - 1);
-                const int p = e / R, i = e - p * R;
-                const int col = min(j0 + p, kd);
-                const double* src = (col == kd) ? a.c + min(i, s - 1)
-                                  : (i < s ? a.Z + (long long)col * s + i : a.F + (long long)col * s + (i - s));
-                v[u] = *src;
+            for (int h = 0; h < 2; ++h) {
+                const int i = min(ib + h * LSB_NT + (int)threadIdx.x, R - 1);
+#pragma unroll
+                for (int p = 0; p < NB; ++p) {
+                    const int col = min(j0 + p, kd);
+                    const double* src = (col == kd) ? a.c + min(i, s - 1)
+                                      : (i < s ? a.Z + (long long)col * s + i : a.F + (long long)col * s + (i - s));
+                    v[h][p] = *src;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * LSB_NT + (int)threadIdx.x;
-                if (e < NB * R) {
-                    const int p = e / R, i = e - p * R;
-                    const int col = j0 + p;
-                    double x = 0.0;
-                    if (col < kd) x = (i < s) ? v[u] : a.lam * v[u];
-                    else if (col == kd && i < s) x = v[u];
-                    P[e] = x;
+            for (int h = 0; h < 2; ++h) {
+                const int i = ib + h * LSB_NT + (int)threadIdx.x;
+                if (i < R) {
+#pragma unroll
+                    for (int p = 0; p < NB; ++p) {
+                        const int col = j0 + p;
+                        double x = 0.0;
+                        if (col < kd) x = (i < s) ? v[h][p] : a.lam * v[h][p];
+                        else if (col == kd && i < s) x = v[h][p];
+                        P[p * RP + i] = x;
+                    }
                 }
             }
         }
@@ -361,7 +457,13 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
         // ---- inside the panel: CholeskyQR2 (column-scaled first stage), or
         // CGS2 column by column for an ill-conditioned panel
         int stages = 0;
-        while (stages < 2 && cholqr_stage(P, R, nb, stages == 0, G, Lm, sc, rcur, rtmp, red, &s_ok)) ++stages;
+        // traced runs: slots 160 + 8 b + 4 stage + (0 .. 3) for panel b < 12
+        unsigned long long* str = (a.trace && j0 / NB < 12) ? a.trace + 160 + 8 * (j0 / NB) : nullptr;
+        while (stages < 2) {
+            unsigned long long* t4 = str ? str + 4 * stages : nullptr;
+            if (!cholqr_stage(P, R, nb, stages == 0, G, Lm, sc, rcur, rtmp, red, &s_ok, t4)) break;
+            ++stages;
+        }
         if (stages < 2) {
             // rtmp accumulates the CGS2 factor of the current P (upper, 16 x 16)
             if (threadIdx.x < 256) rtmp[threadIdx.x] = 0.0;
@@ -373,22 +475,22 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
 #pragma unroll
                         for (int t = 0; t < 16; ++t) part[t] = 0.0;
                         for (int i = threadIdx.x; i < R; i += LSB_NT) {
-                            const double x = P[p * R + i];
+                            const double x = P[p * RP + i];
 #pragma unroll
                             for (int t = 0; t < NB; ++t) {
-                                const double pt = P[t * R + i];
+                                const double pt = P[t * RP + i];
                                 part[t] = fma(t < p ? pt : 0.0, x, part[t]);
                             }
                         }
                         block_multi_sum<16>(part, red, coef);
                         for (int i = threadIdx.x; i < R; i += LSB_NT) {
-                            double x = P[p * R + i];
+                            double x = P[p * RP + i];
 #pragma unroll
                             for (int t = 0; t < NB; ++t) {
-                                const double pt = P[t * R + i];
+                                const double pt = P[t * RP + i];
                                 x = fma(t < p ? -coef[t] : 0.0, pt, x);
                             }
-                            P[p * R + i] = x;
+                            P[p * RP + i] = x;
                         }
                         if (threadIdx.x < p) rtmp[threadIdx.x * 16 + p] += coef[threadIdx.x];
                         __syncthreads();
@@ -396,12 +498,12 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
                 }
                 double nn = 0.0;
                 for (int i = threadIdx.x; i < R; i += LSB_NT) {
-                    const double x = P[p * R + i];
+                    const double x = P[p * RP + i];
                     nn = fma(x, x, nn);
                 }
                 const double nrm = sqrt(block_sum1(nn, red));
                 if (nrm > 0.0 && isfinite(nrm))
-                    for (int i = threadIdx.x; i < R; i += LSB_NT) P[p * R + i] = P[p * R + i] / nrm;
+                    for (int i = threadIdx.x; i < R; i += LSB_NT) P[p * RP + i] = P[p * RP + i] / nrm;
                 if (threadIdx.x == 0) rtmp[p * 16 + p] = nrm;
                 __syncthreads();
             }
@@ -441,7 +543,7 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
         // ---- the panel's orthonormal columns join Q; its R columns (and d)
         for (int e = threadIdx.x; e < R * NB; e += LSB_NT) {
             const int i = e / NB, p = e - i * NB;
-            if (p < nb && j0 + p < kd) Q[(long long)i * k + j0 + p] = P[p * R + i];
+            if (p < nb && j0 + p < kd) Q[(long long)i * k + j0 + p] = P[p * RP + i];
         }
         for (int e = threadIdx.x; e < (j0 + nb) * nb; e += LSB_NT) {
             const int c = e / nb, p = e - c * nb;
@@ -513,7 +615,7 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
 // LDS bytes of the blocked kernel (panel width 16)
 static size_t lsb_bytes(int rows, int k)
 {
-    return sizeof(double) * ((size_t)PNB * rows + 2 * (size_t)(k + 1) * PNB + (size_t)LSB_NW * 256 + 4 * 256 + 32);
+    return sizeof(double) * ((size_t)PNB * panel_ld(rows) + 2 * (size_t)(k + 1) * PNB + (size_t)LSB_NW * 256 + 4 * 256 + 32);
 }
 
 int small_ls_panel(int s, int k, double lam, size_t lds_max)
