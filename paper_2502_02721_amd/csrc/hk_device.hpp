@@ -475,14 +475,17 @@ __device__ __forceinline__ void blur_tile(const TS* __restrict__ x, int ny, int 
 template <typename TV, typename TX>
 __device__ void csr_tile_wave2(const int64_t* __restrict__ rp, const int* __restrict__ ci,
                                const TV* __restrict__ cv, const TX* __restrict__ x, const Tile& ti,
-                               double* wt)
+                               double* wt, const int* rpl, long long rbase)
 {
     constexpr int B = 8;                           // entries per lane per row and batch
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // row pointers from the LDS copy when staged (one LDS read instead of a
+    // global round trip per row pair)
+    auto rowp = [&](int e) -> long long { return rpl ? rbase + rpl[e] : rp[ti.start + e]; };
     for (int e0 = 2 * wave; e0 < ti.E; e0 += 2 * NWAVE) {
         const bool two = e0 + 1 < ti.E;
-        const long long pa = rp[ti.start + e0], pm = rp[ti.start + e0 + 1];
-        const long long pb = two ? rp[ti.start + e0 + 2] : pm;
+        const long long pa = rowp(e0), pm = rowp(e0 + 1);
+        const long long pb = two ? rowp(e0 + 2) : pm;
         const long long na = pm - pa, nb = pb - pm;      // entries of row e0 and e0+1
         double acca = 0.0, accb = 0.0;
         for (long long b0 = 0; b0 < na || b0 < nb; b0 += 64 * B) {
@@ -536,13 +539,14 @@ __device__ void csr_tile_wave2(const int64_t* __restrict__ rp, const int* __rest
 }
 
 // CSR rows [start, start+E): groups of `lpr` lanes per row, FP64 accumulation.
+// rpl (optional): the tile's row pointers in LDS, relative to rbase.
 template <typename TV, typename TX>
 __device__ __forceinline__ void csr_tile(const int64_t* __restrict__ rp, const int* __restrict__ ci,
                          const TV* __restrict__ cv, const TX* __restrict__ x, const Tile& ti,
-                         int lpr, double* wt)
+                         int lpr, double* wt, const int* rpl = nullptr, long long rbase = 0)
 {
     if (lpr == 64) {
-        csr_tile_wave2<TV, TX>(rp, ci, cv, x, ti, wt);
+        csr_tile_wave2<TV, TX>(rp, ci, cv, x, ti, wt, rpl, rbase);
         return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -552,7 +556,8 @@ __device__ __forceinline__ void csr_tile(const int64_t* __restrict__ rp, const i
         const int e = base + sub;
         double acc = 0.0;
         if (e < ti.E) {
-            const long long p0 = rp[ti.start + e], p1 = rp[ti.start + e + 1];
+            const long long p0 = rpl ? rbase + rpl[e] : rp[ti.start + e];
+            const long long p1 = rpl ? rbase + rpl[e + 1] : rp[ti.start + e + 1];
             long long p = p0 + sl;
             // batches of 4 entries per lane: indices and values, then the
             // gathers, then the FMAs (in entry order)
@@ -1304,16 +1309,35 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
     const long long ldd = rect ? a.ldd : a.ldl;
     const double inv_sk = (SK == SK_SPARSE) ? 1.0 / sqrt((double)a.zeta) : 1.0 / sqrt((double)a.s);
 
+    // CSR: the tiles' row pointers are staged in LDS once (relative to the
+    // tile's first entry, when the tile holds fewer than 2^31 entries)
+    const int* rpl_m = nullptr;
+    const int* rpl_n = nullptr;
+    long long rb_m = 0, rb_n = 0;
+    if constexpr (OP == OP_CSR) {
+        auto stage_rp = [&](const int64_t* rp, const Tile& ti, int off, const int*& dst, long long& base) {
+            if (off < 0) return;
+            base = rp[ti.start];
+            if (rp[ti.start + ti.E] - base >= 0x7fffffffLL) return;   // uniform over the workgroup
+            int* l = (int*)(smem + off);
+            for (int e = threadIdx.x; e <= ti.E; e += NT) l[e] = (int)(rp[ti.start + e] - base);
+            dst = l;
+        };
+        stage_rp(a.rp, tm, a.lds_rp_m, rpl_m, rb_m);
+        if (rect) stage_rp(a.rpt, tn, a.lds_rp_n, rpl_n, rb_n);
+        __syncthreads();
+    }
     auto op_forward = [&](const TB* xin) {   // wt = A xin on the m-tile
         if constexpr (OP == OP_BLUR) {
             blur_tile<TB>(xin, a.ny, a.nx, a.r, a.bc, tm, a.spm.TY, a.spm.TX, taps,
                           taps + 2 * a.r + 1, stage, vert, wt);
         } else {
-            csr_tile<TO, TB>(a.rp, a.ci, (const TO*)a.cv, xin, tm, a.lpr, wt);
+            csr_tile<TO, TB>(a.rp, a.ci, (const TO*)a.cv, xin, tm, a.lpr, wt, rpl_m, rb_m);
         }
     };
     auto op_adjoint = [&](const TB* xin) {   // wt = A^T xin on the n-tile
-        if constexpr (OP == OP_CSR) csr_tile<TO, TB>(a.rpt, a.cit, (const TO*)a.cvt, xin, tn, a.lprt, wt);
+        if constexpr (OP == OP_CSR)
+            csr_tile<TO, TB>(a.rpt, a.cit, (const TO*)a.cvt, xin, tn, a.lprt, wt, rpl_n, rb_n);
     };
     auto finish = [&](int k_done, int status, int nt, int ng) {
         if (tile == 0 && threadIdx.x == 0) {
@@ -1355,7 +1379,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
     if constexpr (SAMP) publish(acc, a.spm, tm, pm.bits, a.m, 0, 0);
     if (rect) {
         if constexpr (OP == OP_CSR)                        // v0 = A^T b
-            csr_tile<TO, TO>(a.rpt, a.cit, (const TO*)a.cvt, bvec, tn, a.lprt, wt);
+            csr_tile<TO, TO>(a.rpt, a.cit, (const TO*)a.cvt, bvec, tn, a.lprt, wt, rpl_n, rb_n);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) accn[i] = ((vn >> i) & 1u) ? wt[threadIdx.x + i * NT] : 0.0;
         tile_argmax<EPT>(accn, gn, vn, a.amv, a.ami, G + tile);

@@ -123,6 +123,10 @@ struct KArgs {
     int nslot, spx;             // slots per pivot, slots per row of the window box
     int lds_scale, lds_hs, lds_wred;
     int lds_skt;                // sparse-sign tables (0: built on the fly)
+    // CSR operators: the row pointers of the workgroup's m-tile and n-tile
+    // rows, relative to the tile's first entry (int32), staged once per solve
+    // (-1: not staged, read from global memory)
+    int lds_rp_m, lds_rp_n;
 };
 
 // Column-packed strict lower triangle of a (k+1) x (k+1) pivot block:

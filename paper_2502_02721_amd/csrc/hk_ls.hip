@@ -81,8 +81,8 @@ __device__ __forceinline__ double block_sum1(double v, double* red)
 
 // W[c * 16 + p] = sum_i Q[i * QS + c] P[p * RP + i] for c < j0 (MFMA: A = Q^T
 // block, B = P block, K = rows).  Work units: ncb column blocks x nsplit row
-// groups, unit u on wave u % 8; row-group partials are summed through red (at
-// most 8 x 256 doubles, nsplit > 1 only when ncb * nsplit <= 8).  A unit
+// groups, unit u on wave u % 8; row-group partials are summed in group order
+// through red (at most 8 x 256 doubles).  A unit
 // takes its rows in batches of TNK MFMA K steps (4 rows each) whose loads are
 // all issued before the first product; rows past the unit's end are read at
 // a clamped address and contribute exact zeros.
@@ -91,13 +91,17 @@ __device__ void proj_tn(const double* __restrict__ Q, int QS, int R, int j0, con
     // wave-uniform loop control (scalar branches)
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ncb = (j0 + 15) >> 4;
-    const int nsplit = max(1, LSB_NW / ncb);
+    // 5..7 column blocks: two row halves each, so the 10..14 units spread
+    // over the four SIMDs more evenly than 5..7 whole units on 8 waves; the
+    // first half's sums go to W, the second half's to red (one slot per block)
+    const bool halves = ncb > LSB_NW / 2 && ncb < LSB_NW;
+    const int nsplit = halves ? 2 : max(1, LSB_NW / ncb);
     const int rows_per = (((R + nsplit - 1) / nsplit) + 3) & ~3;
     const int li = lane & 15, lk = lane >> 4;
     const int nun = ncb * nsplit;
     const int nu = wave < nun ? (nun - 1 - wave) / LSB_NW + 1 : 0;   // units of this wave
-    // rows of a unit: [g rows_per, min(R, (g + 1) rows_per)); with nsplit > 1
-    // the wave holds one unit (g = wave % nsplit), otherwise every unit has all R
+    // rows of a unit: [g rows_per, min(R, (g + 1) rows_per)), g = wave % nsplit
+    // for every unit of the wave (units u and u + 8 share g); nsplit = 1: all R
     const int gw = nsplit > 1 ? wave % nsplit : 0;
     const int r0 = gw * rows_per, r1 = min(R, r0 + rows_per);
     for (int q = 0; q < nu; ++q) {
@@ -122,18 +126,26 @@ __device__ void proj_tn(const double* __restrict__ Q, int QS, int R, int j0, con
                 d = mfma16((cok && rok) ? qa[t] : 0.0, rok ? pb[t] : 0.0, d);
             }
         }
-        if (nsplit == 1) {
+        if (nsplit == 1 || (halves && gw == 0)) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int cr = cb * 16 + lk + 4 * v;
                 if (cr < j0) W[cr * PNB + li] = d[v];
             }
         } else {
+            const int slot = halves ? cb : wave;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) red[wave * 256 + (lk + 4 * v) * 16 + li] = d[v];
+            for (int v = 0; v < 4; ++v) red[slot * 256 + (lk + 4 * v) * 16 + li] = d[v];
         }
     }
-    if (nsplit > 1) {
+    if (halves) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncb * 256; e += LSB_NT) {
+            const int cb = e >> 8, ij = e & 255;
+            const int cr = cb * 16 + (ij >> 4);
+            if (cr < j0) W[cr * PNB + (ij & 15)] += red[cb * 256 + ij];
+        }
+    } else if (nsplit > 1) {
         __syncthreads();
         // unit u = cb * nsplit + g (on wave u) sits in red[u]
         for (int e = threadIdx.x; e < ncb * 256; e += LSB_NT) {

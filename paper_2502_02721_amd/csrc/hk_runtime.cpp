@@ -136,7 +136,7 @@ struct Plan {
 };
 
 int lds_layout(KArgs& a, int kp1, int s, int ept, int rect, int op, int TY, int TX, int r, int dtype,
-               int pmode)
+               int pmode, int rp_stage)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -172,6 +172,11 @@ int lds_layout(KArgs& a, int kp1, int s, int ept, int rect, int op, int TY, int 
     a.pmode = pmode;
     a.lds_pD = take(tri);
     a.lds_pL = (rect && pmode == 0) ? take(tri) : a.lds_pD;
+    a.lds_rp_m = a.lds_rp_n = -1;
+    if (op == OP_CSR && rp_stage) {
+        a.lds_rp_m = take(sizeof(int) * ((size_t)NT * ept + 1));
+        a.lds_rp_n = rect ? take(sizeof(int) * ((size_t)NT * ept + 1)) : a.lds_rp_m;
+    }
     a.lds_total = (int)off;
     return a.lds_total;
 }
@@ -185,6 +190,7 @@ int nslot_of(int r, int TY, int TX) { return spx_of(r, TX) * ((2 * r + 1 + TY - 
 // LDS of the single-barrier blur kernel; 0 if it does not fit.
 int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, int tb, int zeta, size_t lds_max)
 {
+    a.lds_rp_m = a.lds_rp_n = -1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -239,10 +245,17 @@ Plan plan_solve(const hk_op* op, const hk_params* p, int rect, int max_blocks, s
     const int tb = p->basis_dtype;
     // pivot blocks: a persistent LDS copy of each if they fit, else one
     // buffer loaded before each substitution
+    // (CSR row pointers are staged in LDS too when they fit)
     auto layout = [&](int ept, int TY, int TX, int r, int opk) {
-        lds_layout(pl.lds, kp1_of(p), p->s, ept, rect, opk, TY, TX, r, tb, 0);
-        if ((size_t)pl.lds.lds_total > lds_max)
-            lds_layout(pl.lds, kp1_of(p), p->s, ept, rect, opk, TY, TX, r, tb, 1);
+        for (int pmode = 0; pmode < 2; ++pmode) {
+            for (int rps = 1; rps >= 0; --rps) {
+                lds_layout(pl.lds, kp1_of(p), p->s, ept, rect, opk, TY, TX, r, tb, pmode, rps);
+                if ((size_t)pl.lds.lds_total <= lds_max) {
+                    pl.lds_total = pl.lds.lds_total;
+                    return;
+                }
+            }
+        }
         pl.lds_total = pl.lds.lds_total;
     };
     const int kp1 = p->k + 1;
