@@ -422,11 +422,25 @@ __device__ __forceinline__ void blur_tile_staged(const TS* __restrict__ x, int n
         double s0 = (double)col[y0 * SW], s1 = (double)col[min(y0 + 1, SH - 1) * SW],
                s2 = (double)col[min(y0 + 2, SH - 1) * SW];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int b = 0; b < taps; ++b) {
-            const double s3 = (double)col[min(y0 + b + 3, SH - 1) * SW];
-            const double w = tyl[b];
-            a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, s3, a3);
-            s0 = s1; s1 = s2; s2 = s3;
+        // unrolled so that several taps' LDS reads are in flight together;
+        // with TY a multiple of 4 no read needs the clamp
+        if ((TY & 3) == 0) {
+            const TS* src = col + (y0 + 3) * SW;
+#pragma unroll 8
+            for (int b = 0; b < taps; ++b) {
+                const double s3 = (double)src[b * SW];
+                const double w = tyl[b];
+                a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, s3, a3);
+                s0 = s1; s1 = s2; s2 = s3;
+            }
+        } else {
+#pragma unroll 8
+            for (int b = 0; b < taps; ++b) {
+                const double s3 = (double)col[min(y0 + b + 3, SH - 1) * SW];
+                const double w = tyl[b];
+                a0 = fma(w, s0, a0); a1 = fma(w, s1, a1); a2 = fma(w, s2, a2); a3 = fma(w, s3, a3);
+                s0 = s1; s1 = s2; s2 = s3;
+            }
         }
         double* vo = vert + y0 * SW + xx;
         vo[0] = a0;
@@ -444,11 +458,22 @@ __device__ __forceinline__ void blur_tile_staged(const TS* __restrict__ x, int n
         const double* row = vert + yy * SW;
         double s0 = row[x0];
         double a0 = 0.0, a1 = 0.0;
-        for (int b = 0; b < taps; ++b) {
-            const double s1 = row[min(x0 + b + 1, SW - 1)];
-            const double w = txl[b];
-            a0 = fma(w, s0, a0); a1 = fma(w, s1, a1);
-            s0 = s1;
+        if ((TX & 1) == 0) {                       // no read needs the clamp
+#pragma unroll 8
+            for (int b = 0; b < taps; ++b) {
+                const double s1 = row[x0 + b + 1];
+                const double w = txl[b];
+                a0 = fma(w, s0, a0); a1 = fma(w, s1, a1);
+                s0 = s1;
+            }
+        } else {
+#pragma unroll 8
+            for (int b = 0; b < taps; ++b) {
+                const double s1 = row[min(x0 + b + 1, SW - 1)];
+                const double w = txl[b];
+                a0 = fma(w, s0, a0); a1 = fma(w, s1, a1);
+                s0 = s1;
+            }
         }
         wt[yy * TX + x0] = a0;
         if (x0 + 1 < TX) wt[yy * TX + x0 + 1] = a1;
