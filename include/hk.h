@@ -25,7 +25,9 @@
  *    (e.g. torch tensors on that GPU); "host" pointers are ordinary memory.
  *  - The library copies every operator input it is given (taps, CSR arrays)
  *    and never frees or retains caller memory.  Handles are opaque and are
- *    destroyed exactly once by the caller.
+ *    destroyed exactly once by the caller, dependents first: a solve (and a
+ *    server with requests of the operator) before its operator, operators
+ *    and servers before their context.
  *  - All device work of a context is ordered on the context's HIP stream;
  *    hk_solve_run is asynchronous.  Getters wait for the solve to finish.
  *  - Indices (pivots) are 0-based row indices of the original problem.
@@ -270,7 +272,10 @@ hk_status hk_solve_destroy(hk_solve* sv);
  * A request whose params->max_workgroups is 0 gets an equal share of the
  * units (workgroups / slots), or more if its problem needs more tiles.  The
  * caller keeps b_dev, x_dev and the operator alive until the request has
- * finished; its result is written to x_dev. */
+ * finished; its result is written to x_dev.  A request's solve is ordered
+ * after the work queued on the context's stream when it was submitted (an
+ * event recorded there at submission), so b_dev and x_dev may still be in
+ * production on that stream; work queued there later is not waited for. */
 hk_status hk_server_create(hk_context* ctx, int32_t slots, size_t budget_bytes, int32_t workgroups,
                            hk_server** out);
 hk_status hk_server_destroy(hk_server* srv);   /* waits for the running solves */

@@ -282,21 +282,36 @@ def _torch():
 _DT = {HK_F64: "float64", HK_F32: "float32", HK_BF16: "bfloat16", HK_F16: "float16"}
 
 
-class Context:
-    """A device and a stream (default: torch's current stream on that device)."""
+class _Owner:
+    """Handle lifetime: a handle that others depend on (a context for its
+    operators, an operator for its solves) is destroyed only after the last
+    dependent one, whatever order the garbage collector finalises them in."""
 
-    def __init__(self, device: int = 0, stream=None):
-        torch = _torch()
-        if stream is None:
-            stream = torch.cuda.current_stream(device)
-        self.device = device
-        self.stream = stream
-        self.handle = hk_context_create(device, stream.cuda_stream)
+    handle = None
+
+    def _init_owner(self, parent=None):
+        self._users = 0
+        self._closing = False
+        self._parent = parent
+        if parent is not None:
+            parent._users += 1
+
+    def _destroy(self):
+        raise NotImplementedError
 
     def close(self):
-        if self.handle:
-            hk_context_destroy(self.handle)
-            self.handle = None
+        if not self.handle:
+            return
+        self._closing = True
+        if self._users > 0:
+            return                    # destroyed when the last dependent closes
+        self._destroy()
+        self.handle = None
+        parent, self._parent = self._parent, None
+        if parent is not None:
+            parent._users -= 1
+            if parent._closing:
+                parent.close()
 
     def __del__(self):
         try:
@@ -305,10 +320,31 @@ class Context:
             pass
 
 
-class Operator:
+class Context(_Owner):
+    """A device and a stream (default: torch's current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        self._init_owner()
+        self.handle = hk_context_create(device, stream.cuda_stream)
+
+    def _destroy(self):
+        hk_context_destroy(self.handle)
+
+
+
+class Operator(_Owner):
     def __init__(self, ctx: Context, handle: int, dtype: int):
         self.ctx, self.handle, self.dtype = ctx, handle, dtype
+        self._init_owner(ctx)
         self.m, self.n = hk_op_shape(handle)
+
+    def _destroy(self):
+        hk_op_destroy(self.handle)
 
     @classmethod
     def blur(cls, ctx, ny, nx, taps_y, taps_x, radius, bc, dtype):
@@ -343,19 +379,9 @@ class Operator:
         hk_op_apply(self.handle, 1 if transpose else 0, x.data_ptr(), out.data_ptr())
         return out
 
-    def close(self):
-        if self.handle:
-            hk_op_destroy(self.handle)
-            self.handle = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
-class Solve:
+class Solve(_Owner):
     """A solve of one operator with fixed parameters; run() may be called repeatedly."""
 
     def __init__(self, op: Operator, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
@@ -370,6 +396,10 @@ class Solve:
         self.k, self.s = k, (k + 1 if sketch == HK_SKETCH_NONE else s)
         self.rect = (method == HK_METHOD_CHANGING_HESSENBERG) or (method == HK_METHOD_AUTO and op.m != op.n)
         self.handle = hk_solve_create(op.handle, self.params)
+        self._init_owner(op)
+
+    def _destroy(self):
+        hk_solve_destroy(self.handle)
 
     def workspace_bytes(self) -> int:
         return hk_solve_workspace_bytes(self.op.handle, self.params)
@@ -424,19 +454,8 @@ class Solve:
     def timing_history(self, max_runs: int = 256):
         return hk_solve_timing_history(self.handle, max_runs)
 
-    def close(self):
-        if self.handle:
-            hk_solve_destroy(self.handle)
-            self.handle = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-
-class Server:
+class Server(_Owner):
     """Continuous batching of solves on one device (argument marshalling only;
     admission, streams and workspaces are managed by hk_server_* in the
     library).  Keeps the tensors of each request alive until it finishes."""
@@ -446,6 +465,20 @@ class Server:
         _check(lib().hk_server_create(C.c_void_p(ctx.handle), slots, budget_bytes, workgroups, C.byref(h)))
         self.ctx, self.handle = ctx, h.value
         self._live = {}
+        self._init_owner(ctx)
+
+    def _destroy(self):
+        _check(lib().hk_server_destroy(C.c_void_p(self.handle)))
+        for t in list(self._live):
+            self._release(t)
+
+    def _release(self, ticket):
+        ent = self._live.pop(ticket, None)
+        if ent is not None:
+            op = ent[0]
+            op._users -= 1
+            if op._closing:
+                op.close()
 
     def submit(self, op: Operator, b, x, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
                method=HK_METHOD_AUTO, basis_dtype=None, pivot_sample=0, max_workgroups=0) -> int:
@@ -457,6 +490,7 @@ class Server:
         _check(lib().hk_server_submit(C.c_void_p(self.handle), C.c_void_p(op.handle), C.byref(prm),
                                       C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(t)))
         self._live[t.value] = (op, b, x)
+        op._users += 1            # the operator outlives the request
         return t.value
 
     def poll(self) -> int:
@@ -475,18 +509,7 @@ class Server:
         t0, t1, t2 = C.c_double(), C.c_double(), C.c_double()
         _check(lib().hk_server_result(C.c_void_p(self.handle), ticket, C.byref(st), C.byref(kd), C.byref(g),
                                       C.byref(t0), C.byref(t1), C.byref(t2)))
-        self._live.pop(ticket, None)
+        self._release(ticket)
         return {"status": st.value, "k_done": kd.value, "workgroups": g.value, "t_submit": t0.value,
                 "t_start": t1.value, "t_finish": t2.value}
 
-    def close(self):
-        if self.handle:
-            _check(lib().hk_server_destroy(C.c_void_p(self.handle)))
-            self.handle = None
-            self._live.clear()
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass

@@ -497,12 +497,13 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 if (rect) {
                     const int ya = max(max(py - r, tm.y0), 0), yb = min(min(py + r, tm.y0 + TY - 1), ny - 1);
                     const int xa = max(max(px - r, tm.x0), 0), xb = min(min(px + r, tm.x0 + TX - 1), nx - 1);
-                    const int x = xa + (lane & 31);
-                    if (x <= xb) {
+                    // a window wider than 32 columns (r >= 16) meets a wide
+                    // tile in more columns than a half-wave has lanes
+                    for (int x = xa + (lane & 31); x <= xb; x += 32) {
                         double cs = 0.0;
                         for (int y = ya + (lane >> 5); y <= yb; y += 2)
                             cs = fma(tyl[y - py + r], wt[(y - tm.y0) * TX + (x - tm.x0)], cs);
-                        acc2 = txl[x - px + r] * cs;
+                        acc2 = fma(txl[x - px + r], cs, acc2);
                     }
                 } else {
                     // reflection folds each axis separately: lanes take the

@@ -2,6 +2,8 @@
 // standalone operator products) and the host-side launchers.
 #include "hk_device.hpp"
 
+#include <algorithm>
+
 namespace hk {
 
 // ------------------------------------------------------------------------
@@ -250,6 +252,25 @@ hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KAr
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st)
 {
     hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(256), 0, st, ctl);
+    return hipGetLastError();
+}
+
+// Zero `n16` 16-byte words (a kernel rather than a memset node, so that the
+// sequence stays capturable in a HIP graph).
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint4* p, size_t n16)
+{
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256) p[i] = z;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)p & 15u) || (bytes & 15u)) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16;
+    const size_t want = (n16 + 255) / 256;
+    const unsigned blocks = (unsigned)std::min<size_t>(want, 4096);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, st, (uint4*)p, n16);
     return hipGetLastError();
 }
 

@@ -424,8 +424,6 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
     w.ldd = (int64_t)align_up((size_t)op->m, 64);
     const int rows = p->lambda > 0.0 ? 2 * s : s;
     w.ctl = take(sizeof(Ctl));
-    w.L = take(es * (size_t)w.ldl * kp1);
-    w.D = rect ? take(es * (size_t)w.ldd * kp1) : 0;
     w.H = take(sizeof(double) * (size_t)kp1 * k);
     w.W = take(sizeof(double) * (size_t)k * k);
     w.tp = take(sizeof(int) * kp1);
@@ -461,6 +459,10 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
         w.part = take(sizeof(double) * 4096 * tiles);
     }
     w.sidx = take(sizeof(int) * 4 * SAMPLE_SLOTS);
+    // the bases last: every column a run reads it has written first, so a
+    // reused workspace needs only [0, L) cleared
+    w.L = take(es * (size_t)w.ldl * kp1);
+    w.D = rect ? take(es * (size_t)w.ldd * kp1) : 0;
     w.total = off;
     return w;
 }
@@ -764,25 +766,10 @@ static hk_status solve_plan(hk_op* op, const hk_params* p_in, hk_params* pe, int
     return HK_OK;
 }
 
-// Create a solve.  ws: a device buffer of at least the planned size to use
-// as workspace (zeroed on `stream`), or null to allocate one; nev: runs whose
-// timing events are kept; stream: where runs are ordered.
-static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t ws_cap, int nev,
-                              hipStream_t stream, hk_solve** out)
+// Fill a solve's arguments for the workspace at `base` (laid out as `w`).
+static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rect, const Plan& pl,
+                            const WsLayout& w, unsigned char* base, hipStream_t stream)
 {
-    if (!out) return fail(HK_EINVAL, "null output handle");
-    *out = nullptr;
-    int rect = 0;
-    hk_params pe{};
-    Plan pl;
-    size_t need = 0;
-    hk_status st = solve_plan(op, p_in, &pe, &rect, &pl, &need);
-    if (st) return st;
-    const hk_params* p = &pe;
-    const WsLayout w = ws_layout(op, p, rect, pl.G, pl.nslot);
-    if (ws && ws_cap < w.total) return fail(HK_ENOMEM, "workspace of %zu bytes is smaller than %zu", ws_cap, w.total);
-    auto* sv = new (std::nothrow) hk_solve;
-    if (!sv) return fail(HK_ENOMEM, "host allocation failed");
     sv->op = op;
     sv->prm = *p;
     sv->tb = p->basis_dtype;
@@ -792,28 +779,7 @@ static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t
     sv->kernel = pl.kernel;
     sv->G = pl.G;
     sv->stream = stream;
-    sv->nev = std::max(1, std::min(nev, (int)hk_solve::NEV));
-    if (ws) {
-        sv->ws = ws;
-        sv->own_ws = false;
-    } else if (hipMalloc(&sv->ws, w.total) != hipSuccess) {
-        delete sv;
-        return fail(HK_ENOMEM, "hipMalloc of %zu workspace bytes failed", w.total);
-    }
     sv->ws_bytes = w.total;
-    for (int i = 0; i < sv->nev; ++i)
-        for (int q = 0; q < 3; ++q)
-            if (hipEventCreate(&sv->ev[i][q]) != hipSuccess) {
-                hk_solve_destroy(sv);
-                return fail(HK_EDEVICE, "hipEventCreate failed");
-            }
-    // zero the workspace once (H, W, pivots read back even when unused)
-    const hipError_t ze = sv->own_ws ? hipMemset(sv->ws, 0, w.total) : hipMemsetAsync(sv->ws, 0, w.total, stream);
-    if (ze != hipSuccess) {
-        hk_solve_destroy(sv);
-        return fail(HK_EDEVICE, "zeroing the workspace failed");
-    }
-    unsigned char* base = (unsigned char*)sv->ws;
     KArgs& a = sv->ka;
     a = pl.lds;    // lds_* offsets
     a.m = (int)op->m; a.n = (int)op->n; a.k = p->k; a.s = p->s; a.zeta = p->zeta;
@@ -913,38 +879,72 @@ static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t
     c.n = (int)op->n; c.k = p->k; c.L = a.L; c.ldl = a.ldl; c.y = l.y; c.ctl = a.ctl;
     c.scale = (pl.kernel == OP_BLUR_ONEBAR) ? a.scale : nullptr;
     l.nb = small_ls_panel(p->s, p->k, p->lambda, op->ctx->lds_max);
-    if (l.nb == 0 && (size_t)small_ls_lds_bytes(p->s, p->k, p->lambda) > op->ctx->lds_max) {
-        hk_solve_destroy(sv);
+    if (l.nb == 0 && (size_t)small_ls_lds_bytes(p->s, p->k, p->lambda) > op->ctx->lds_max)
         return fail(HK_EUNSUPPORTED, "sketch size too large for the least-squares kernel's LDS");
+    return HK_OK;
+}
+
+// Create a solve.  ws: a device buffer of at least the planned size to use
+// as workspace (zeroed on `stream`), or null to allocate one; nev: runs whose
+// timing events are kept; stream: where runs are ordered.
+static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t ws_cap, int nev,
+                              hipStream_t stream, hk_solve** out)
+{
+    if (!out) return fail(HK_EINVAL, "null output handle");
+    *out = nullptr;
+    int rect = 0;
+    hk_params pe{};
+    Plan pl;
+    size_t need = 0;
+    hk_status st = solve_plan(op, p_in, &pe, &rect, &pl, &need);
+    if (st) return st;
+    const hk_params* p = &pe;
+    const WsLayout w = ws_layout(op, p, rect, pl.G, pl.nslot);
+    if (ws && ws_cap < w.total) return fail(HK_ENOMEM, "workspace of %zu bytes is smaller than %zu", ws_cap, w.total);
+    auto* sv = new (std::nothrow) hk_solve;
+    if (!sv) return fail(HK_ENOMEM, "host allocation failed");
+    sv->op = op;
+    sv->nev = std::max(1, std::min(nev, (int)hk_solve::NEV));
+    if (ws) {
+        sv->ws = ws;
+        sv->own_ws = false;
+    } else if (hipMalloc(&sv->ws, w.total) != hipSuccess) {
+        delete sv;
+        return fail(HK_ENOMEM, "hipMalloc of %zu workspace bytes failed", w.total);
+    }
+    for (int i = 0; i < sv->nev; ++i)
+        for (int q = 0; q < 3; ++q)
+            if (hipEventCreate(&sv->ev[i][q]) != hipSuccess) {
+                hk_solve_destroy(sv);
+                return fail(HK_EDEVICE, "hipEventCreate failed");
+            }
+    // zero the workspace once (H, W, pivots read back even when unused)
+    const hipError_t ze = sv->own_ws ? hipMemset(sv->ws, 0, w.total) : launch_fill_zero(sv->ws, w.total, stream);
+    if (ze != hipSuccess) {
+        hk_solve_destroy(sv);
+        return fail(HK_EDEVICE, "zeroing the workspace failed");
+    }
+    st = solve_bind(sv, op, p, rect, pl, w, (unsigned char*)sv->ws, stream);
+    if (st) {
+        hk_solve_destroy(sv);
+        return st;
     }
     *out = sv;
     return HK_OK;
 }
 
-extern "C" {
-
-hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
+// Enqueue one run on `s`: control reset, basis kernel, sketches at the end,
+// small least squares, x = L_k y.  Events (optional) bracket the basis
+// kernel and the run.
+static hk_status solve_enqueue(hk_solve* sv, const void* b_dev, void* x_dev, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1, hipEvent_t e2)
 {
-    if (!op) return fail(HK_EINVAL, "null operator");
-    return solve_create(op, p, nullptr, 0, hk_solve::NEV, op->ctx->stream, out);
-}
-
-hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
-{
-    if (!sv || !b_dev || !x_dev) return fail(HK_EINVAL, "null argument");
-    hk_status st = current_device(sv->op->ctx);
-    if (st) return st;
-    hipStream_t s = sv->stream;
     KArgs a = sv->ka;
     a.b = b_dev;
-    const int slot = (int)(sv->runs % sv->nev);
-    sv->ev0 = sv->ev[slot][0];
-    sv->ev1 = sv->ev[slot][1];
-    sv->ev2 = sv->ev[slot][2];
     HIP_TRY(launch_ctl_init(a.ctl, s));
-    HIP_TRY(hipEventRecord(sv->ev0, s));
+    if (e0) HIP_TRY(hipEventRecord(e0, s));
     HIP_TRY(launch_iterate(sv->tb, sv->op->dtype, sv->kernel, sv->sk, sv->ept, a, s));
-    HIP_TRY(hipEventRecord(sv->ev1, s));
+    if (e1) HIP_TRY(hipEventRecord(e1, s));
     if (a.nosk) HIP_TRY(launch_hess_rhs(a.F, a.c, sv->prm.s, sv->prm.k, sv->prm.lambda, a.ctl, s));
     if (sv->zend) {
         // Gaussian sketches of the whole basis: Z = (S2 D_{k+1}) H_{k+1,k},
@@ -964,7 +964,29 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
     CombineArgs c = sv->ca;
     c.x = x_dev;
     HIP_TRY(launch_combine(sv->tb, sv->op->dtype, c, s));
-    HIP_TRY(hipEventRecord(sv->ev2, s));
+    if (e2) HIP_TRY(hipEventRecord(e2, s));
+    return HK_OK;
+}
+
+extern "C" {
+
+hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
+{
+    if (!op) return fail(HK_EINVAL, "null operator");
+    return solve_create(op, p, nullptr, 0, hk_solve::NEV, op->ctx->stream, out);
+}
+
+hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
+{
+    if (!sv || !b_dev || !x_dev) return fail(HK_EINVAL, "null argument");
+    hk_status st = current_device(sv->op->ctx);
+    if (st) return st;
+    const int slot = (int)(sv->runs % sv->nev);
+    sv->ev0 = sv->ev[slot][0];
+    sv->ev1 = sv->ev[slot][1];
+    sv->ev2 = sv->ev[slot][2];
+    st = solve_enqueue(sv, b_dev, x_dev, sv->stream, sv->ev0, sv->ev1, sv->ev2);
+    if (st) return st;
     sv->runs++;
     sv->ran = true;
     sv->waited = false;
@@ -1186,6 +1208,7 @@ struct hk_server {
         hk_params p;
         const void* b;
         void* x;
+        hipEvent_t ready;           // the context stream at submission (b and x produced)
     };
     std::deque<Req> queue;
     struct Res {
@@ -1196,6 +1219,7 @@ struct hk_server {
     };
     std::vector<Res> res;
     std::vector<std::pair<void*, size_t>> pool;   // idle workspaces
+    std::vector<hipEvent_t> evpool;               // idle submission events
     int64_t completed = 0;
     int running = 0;
 };
@@ -1260,6 +1284,7 @@ hk_status server_pump(hk_server* s)
         }
         if (st < 0) {
             s->queue.pop_front();
+            s->evpool.push_back(rq.ready);
             finish_request(s, rq.ticket, st, 0);
             continue;
         }
@@ -1286,20 +1311,27 @@ hk_status server_pump(hk_server* s)
             if (s->held + need > s->budget) {
                 if (s->running > 0) break;                      // wait for memory
                 s->queue.pop_front();
+                s->evpool.push_back(rq.ready);
                 finish_request(s, rq.ticket, fail(HK_ENOMEM, "workspace of %zu bytes exceeds the budget", need), 0);
                 continue;
             }
             if (hipMalloc(&buf, need) != hipSuccess) {
                 if (s->running > 0) break;
                 s->queue.pop_front();
+                s->evpool.push_back(rq.ready);
                 finish_request(s, rq.ticket, fail(HK_ENOMEM, "hipMalloc of %zu bytes failed", need), 0);
                 continue;
             }
             cap = need;
             s->held += need;
         }
+        // the slot stream starts after everything the caller's stream held
+        // at submission (whatever produced b and x)
+        const hipError_t we = hipStreamWaitEvent(slot->st, rq.ready, 0);
+        s->evpool.push_back(rq.ready);
         hk_solve* sv = nullptr;
-        st = solve_create(rq.op, &p, buf, cap, 1, slot->st, &sv);
+        st = we == hipSuccess ? solve_create(rq.op, &p, buf, cap, 1, slot->st, &sv)
+                              : fail(HK_EDEVICE, "hipStreamWaitEvent failed: %s", hipGetErrorString(we));
         if (st == HK_OK) {
             st = hk_solve_run(sv, rq.b, rq.x);
             if (st != HK_OK) {
@@ -1371,6 +1403,8 @@ hk_status hk_server_destroy(hk_server* s)
         if (sl.st) hipStreamDestroy(sl.st);
     }
     for (auto& b : s->pool) hipFree(b.first);
+    for (auto& rq : s->queue) hipEventDestroy(rq.ready);
+    for (hipEvent_t e : s->evpool) hipEventDestroy(e);
     delete s;
     return HK_OK;
 }
@@ -1382,10 +1416,22 @@ hk_status hk_server_submit(hk_server* s, hk_op* op, const hk_params* params, con
     if (op->ctx->device != s->ctx->device) return fail(HK_EINVAL, "the operator lives on another device");
     hk_status st = current_device(s->ctx);
     if (st) return st;
+    // an event on the context stream marks what the solve must follow
+    hipEvent_t ev = nullptr;
+    if (!s->evpool.empty()) {
+        ev = s->evpool.back();
+        s->evpool.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        return fail(HK_EDEVICE, "hipEventCreateWithFlags failed");
+    }
+    if (hipEventRecord(ev, s->ctx->stream) != hipSuccess) {
+        s->evpool.push_back(ev);
+        return fail(HK_EDEVICE, "hipEventRecord on the context stream failed");
+    }
     const int64_t t = (int64_t)s->res.size();
     s->res.emplace_back();
     s->res.back().t_submit = now_s();
-    s->queue.push_back({t, op, *params, b_dev, x_dev});
+    s->queue.push_back({t, op, *params, b_dev, x_dev, ev});
     *ticket = t;
     return server_pump(s);
 }

@@ -2,6 +2,9 @@
 compare it with the oracle on the same inputs (not collected by pytest)."""
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 
 import workloads as W
@@ -40,30 +43,33 @@ def make_operator(hk, ctx, P):
     return hk.Operator.csr(ctx, P.m, P.n, P.rowptr, P.col, P.val.astype(storage_np(P.dtype)), dt)
 
 
-def gpu_solve(hk, ctx, P, method=0, keep_basis=True, runs=1):
+def gpu_solve(hk, ctx, P, method=0, keep_basis=True, runs=1, max_workgroups=0):
     import torch
     op = make_operator(hk, ctx, P)
     bdt = hk.HK_F64 if P.basis_dtype == "f64" else hk.HK_F32
     sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, method, basis_dtype=bdt,
-                  pivot_sample=P.pivot_sample)
-    b = torch.tensor(P.b.astype(storage_np(P.dtype)), device=f"cuda:{ctx.device}")
-    xs = []
-    for _ in range(runs):
-        x = sv.run(b)
-        st = sv.wait()
-        xs.append(x.detach().cpu().numpy().astype(np.float64))
-    out = {"x": xs[-1], "xs": xs, "status": st, "k_done": sv.k_done()}
-    out["H"], out["W"] = sv.hessenberg()
-    out["t"], out["g"] = sv.pivots()
-    out["res"] = sv.residuals()
-    out["Z"], out["F"], out["c"] = sv.sketches()
-    if keep_basis:
-        out["L"] = sv.basis(0).detach().cpu().numpy().astype(np.float64).T
-        if sv.rect:
-            out["D"] = sv.basis(1).detach().cpu().numpy().astype(np.float64).T
-    out["timing"] = sv.timing()
-    sv.close()
-    op.close()
+                  pivot_sample=P.pivot_sample, max_workgroups=max_workgroups)
+    try:
+        b = torch.tensor(P.b.astype(storage_np(P.dtype)), device=f"cuda:{ctx.device}")
+        xs = []
+        for _ in range(runs):
+            x = sv.run(b)
+            st = sv.wait()
+            xs.append(x.detach().cpu().numpy().astype(np.float64))
+        out = {"x": xs[-1], "xs": xs, "status": st, "k_done": sv.k_done()}
+        out["H"], out["W"] = sv.hessenberg()
+        out["t"], out["g"] = sv.pivots()
+        out["res"] = sv.residuals()
+        out["Z"], out["F"], out["c"] = sv.sketches()
+        if keep_basis:
+            out["L"] = sv.basis(0).detach().cpu().numpy().astype(np.float64).T
+            if sv.rect:
+                out["D"] = sv.basis(1).detach().cpu().numpy().astype(np.float64).T
+        out["timing"] = sv.timing()
+        out["grid"] = sv.grid()
+    finally:
+        sv.close()
+        op.close()
     return out
 
 
@@ -120,16 +126,39 @@ def sensitivity_bars(name):
     return {"tau": 2.0 * basis, "mid": 2.0 * mid}
 
 
+def col_maxrel(A, B):
+    """Largest column-wise elementwise difference, relative to the column's
+    largest magnitude: max_j max_r |A(r, j) - B(r, j)| / max_r |B(r, j)|."""
+    if not A.size:
+        return 0.0
+    nb = np.maximum(np.max(np.abs(B), axis=0), 1e-300)
+    return float(np.max(np.max(np.abs(A - B), axis=0) / nb))
+
+
+def basis_agree(g_piv, o_piv):
+    """Basis columns whose pivot agrees: column j is v_j normalised at its
+    pivot, so the leading columns up to the first mismatch are comparable."""
+    i = first_mismatch([int(v) for v in g_piv if v >= 0], [int(v) for v in o_piv])
+    return len(o_piv) if i is None else i
+
+
+# measured deviations of the last compare_solve (for reports)
+LAST = {}
+
+
 def compare_solve(P, g, o, bars=None):
     """Element-by-element comparison of a GPU solve with the oracle.  All
     diagnostics are printed before any assertion.  `bars` may widen the
     near-tie and intermediate bars of a rounding-sensitive workload (see
-    sensitivity_bars); the bar on x is always the class bar."""
+    sensitivity_bars); the bar on x is always the class bar, both as a
+    relative 2-norm and elementwise relative to max |x|."""
     cls = P.dtype                      # precision class of the workload
     tau = max(TAU[cls], (bars or {}).get("tau", 0.0))
     mid = max(MID_TOL[cls], (bars or {}).get("mid", 0.0))
     kd = o["k_done"]
     err = rel(g["x"], o["x"])
+    xmax = float(np.max(np.abs(o["x"]))) if o["x"].size else 0.0
+    emax = float(np.max(np.abs(g["x"] - o["x"]))) / (xmax if xmax > 0 else 1.0)
     nL = o["Lmat"] if o["method"] == 0 else o["Dmat"]
     gp = [int(v) for v in g["t"] if v >= 0]
     i = first_mismatch(gp, [int(v) for v in o["t"]])
@@ -144,12 +173,37 @@ def compare_solve(P, g, o, bars=None):
     ef = col_rel(g["F"][:, :m], o["F"][:, :m]) if P.lam > 0 else 0.0
     er = float(np.max(np.abs(g["res"][:m] - o["res"][:m]) / np.maximum(o["res"][:m], 1e-300))) if m else 0.0
     ec = rel(g["c"], o["c"])
-    print(f"  k_done {g['k_done']}/{kd} status {g['status']}/{o['status']} x_err {err:.3e} "
+    # bases, column by column, elementwise, on the agreed pivot prefix: L for
+    # sCMRH, D (data space) and L for sLSLU
+    eb = 0.0
+    nb_cols = 0
+    if "L" in g:
+        if o["method"] == 0:
+            nc = min(agree, o["Lmat"].shape[1], g["L"].shape[1])
+            eb = col_maxrel(g["L"][:, :nc], o["Lmat"][:, :nc])
+            nb_cols = nc
+        else:
+            nd = min(agree, o["Dmat"].shape[1], g["D"].shape[1])
+            ag = basis_agree(g["g"], o["g"])
+            nl = min(ag, len(o["g"]), o["Lmat"].shape[1], g["L"].shape[1])
+            eb = max(col_maxrel(g["D"][:, :nd], o["Dmat"][:, :nd]),
+                     col_maxrel(g["L"][:, :nl], o["Lmat"][:, :nl]))
+            nb_cols = nd + nl
+    LAST.clear()
+    LAST.update(x=err, xmax=emax, H=eH, Z=ez, F=ef, res=er, c=ec, basis=eb, basis_cols=nb_cols,
+                agree=agree, k_done=kd)
+    log = os.environ.get("HK_PARITY_LOG")
+    if log:   # measured deviations, one JSON line per comparison
+        with open(log, "a") as f:
+            f.write(json.dumps({"name": P.name, "dtype": P.dtype, "basis_dtype": P.basis_dtype, "m": P.m, "n": P.n,
+                                "k": P.k, "s": P.s, "lam": P.lam, "sketch": P.sketch, **LAST}) + "\n")
+    print(f"  k_done {g['k_done']}/{kd} status {g['status']}/{o['status']} x_err {err:.3e} x_max {emax:.3e} "
           f"first_pivot_mismatch {i} near {near} H {eH:.2e} Z {ez:.2e} F {ef:.2e} res {er:.2e} "
-          f"c {ec:.2e}", flush=True)
+          f"c {ec:.2e} basis {eb:.2e} ({nb_cols} cols)", flush=True)
     assert g["k_done"] == kd, (g["k_done"], kd)
     assert (g["status"] == 1) == (o["status"] == 1)
     assert err <= X_TOL[cls], f"relative solution error {err:.3e} > {X_TOL[cls]:.0e}"
+    assert emax <= X_TOL[cls], f"elementwise solution error {emax:.3e} > {X_TOL[cls]:.0e} max|x|"
     if i is not None:
         assert near is not None and near <= tau, f"pivot {i} mismatch is not a near-tie ({near})"
     if o["method"] == 1:
@@ -163,6 +217,7 @@ def compare_solve(P, g, o, bars=None):
     assert ez <= mid, f"Z differs: {ez:.3e}"
     assert ef <= mid, f"F differs: {ef:.3e}"
     assert er <= mid, f"residual history differs: {er:.3e}"
+    assert eb <= mid, f"basis differs: {eb:.3e}"
     # S2 b depends on b only; FP32-class workloads evaluate the Gaussian
     # entries in FP32 (about 1e-7 relative), FP64 workloads in FP64
     assert ec <= (1e-13 if P.dtype == "f64" else 1e-6), f"S2 b differs: {ec:.3e}"

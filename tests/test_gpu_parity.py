@@ -70,11 +70,12 @@ def test_csr_apply_and_transpose(hk, ctx, orc, dtype):
 
 
 # ---------------------------------------------------------------- sCMRH
-def _parity(hk, ctx, orc, P, method=0, bars=None):
-    _flush(f"solve {P.name} m={P.m} n={P.n} k={P.k} s={P.s} lam={P.lam} sketch={P.sketch} {P.dtype}")
+def _parity(hk, ctx, orc, P, method=0, bars=None, max_workgroups=0):
+    _flush(f"solve {P.name} m={P.m} n={P.n} k={P.k} s={P.s} lam={P.lam} sketch={P.sketch} {P.dtype} "
+           f"max_workgroups={max_workgroups}")
     Pr = rounded_problem(P)
     o = orc.solve(Pr, keep_basis=True, method=None if method == 0 else (0 if method == 1 else 1))
-    g = gpu_solve(hk, ctx, P, method=method)
+    g = gpu_solve(hk, ctx, P, method=method, max_workgroups=max_workgroups)
     err = compare_solve(Pr, g, o, bars)
     _flush(f"  rel x err {err:.3e}, k_done {g['k_done']}")
     return g, o
@@ -224,6 +225,50 @@ def test_largest_image(hk, ctx, orc):
     P = tiny_blur(1024, 512, 2.0, 7, W.BC_REFLECT, k=12, s=48, lam=1e-2, sketch=W.SKETCH_SPARSE_SIGN,
                   zeta=8, dtype="f32")
     _parity(hk, ctx, orc, P)
+
+
+@pytest.mark.parametrize("r,bc,dtype,sketch", [(16, W.BC_ZERO, "f64", W.SKETCH_SPARSE_SIGN),
+                                               (20, W.BC_REFLECT, "f32", W.SKETCH_SPARSE_SIGN),
+                                               (23, W.BC_ZERO, "f32", W.SKETCH_GAUSSIAN)])
+def test_wide_stencil_windows(hk, ctx, orc, r, bc, dtype, sketch):
+    # a grid capped at 128 workgroups tiles the 512 x 512 image in 32 x 64
+    # tiles, so a (2r+1)-wide window with r >= 16 meets a tile in more than
+    # 32 columns: the window sums of u at the pivots take several column
+    # passes per lane (the single-barrier kernel's LDS plan fits these
+    # cases: zeta = 4 keeps the sparse-sign row lists at 32 KiB)
+    P = tiny_blur(512, 512, (r + 1) / 4.0, r, bc, k=12, s=48, lam=1e-2, sketch=sketch,
+                  zeta=4, dtype=dtype)
+    g, _ = _parity(hk, ctx, orc, P, max_workgroups=128)
+    assert g["grid"] == 128
+
+
+@pytest.mark.parametrize("kind,bad", [("blur", np.nan), ("blur", np.inf), ("csr", np.nan), ("csr", -np.inf)])
+def test_nonfinite_rhs_is_numeric_error(hk, ctx, kind, bad):
+    if kind == "blur":
+        P = tiny_blur(64, 64, 2.0, 7, W.BC_REFLECT, k=10, s=40, sketch=W.SKETCH_SPARSE_SIGN, dtype="f32")
+    else:
+        P = random_csr(900, 613, 0.02, k=10, s=30, dtype="f64")
+    b = P.b.copy()
+    b[len(b) // 3] = bad
+    with pytest.raises(hk.HKError) as e:
+        gpu_solve(hk, ctx, P.replace(b=b), keep_basis=False)
+    _flush(f"  {kind} with {bad} in b: status {e.value.status}")
+    assert e.value.status == hk.HK_ENUMERIC
+
+
+def test_rank_deficient_small_problem(hk, ctx, orc):
+    # b lies in the null space of A: A l_1 = 0 ends the basis after one
+    # column and the sketched problem's only column S2 A l_1 is zero
+    n = 300
+    d = np.arange(1.0, n + 1)
+    d[123] = 0.0
+    b = np.zeros(n); b[123] = 2.0
+    P = W.dense_problem("nullspace", np.diag(d), b, k=5, s=12)
+    with pytest.raises(RuntimeError):
+        orc.solve(P, method=0)            # the oracle reports it too (R_11 = 0)
+    with pytest.raises(hk.HKError) as e:
+        gpu_solve(hk, ctx, P, method=hk.HK_METHOD_HESSENBERG, keep_basis=False)
+    assert e.value.status == hk.HK_ENUMERIC
 
 
 def test_large_sketch_column_ls(hk, ctx, orc):

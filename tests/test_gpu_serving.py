@@ -100,15 +100,48 @@ def test_mix_equals_alone_and_overlaps(hk, ctx, orc):
     for i, (op, P, (b, x)) in enumerate(zip(ops, probs, bufs)):
         xa = _alone(hk, op, P, b)
         assert torch.equal(x, xa), f"request {i} ({P.name}): mix and alone differ by {rel(x.cpu().numpy(), xa.cpu().numpy()):.3e}"
-    # the mix agrees with the oracle at the class bars
-    for i in (0, 3, 5):
-        P = probs[i]
-        o = orc.solve(rounded_problem(P), method=None)
-        err = rel(bufs[i][1].cpu().numpy().astype(np.float64), o["x"])
-        _flush(f"  request {i} ({P.name}, {P.dtype}) vs oracle {err:.3e}")
-        assert err <= (1e-10 if P.dtype == "f64" else 1e-4)
+    # every request of the mix agrees with the oracle at its class bar, as a
+    # relative 2-norm and elementwise relative to max |x|
+    cache = {}
+    for i, P in enumerate(probs):
+        key = id(P)
+        if key not in cache:
+            cache[key] = orc.solve(rounded_problem(P), method=None)
+        o = cache[key]
+        xg = bufs[i][1].cpu().numpy().astype(np.float64)
+        err = rel(xg, o["x"])
+        emax = float(np.max(np.abs(xg - o["x"])) / max(np.max(np.abs(o["x"])), 1e-300))
+        bar = 1e-10 if P.dtype == "f64" else 1e-4
+        _flush(f"  request {i} ({P.name}, {P.dtype}) vs oracle {err:.3e} elementwise {emax:.3e}")
+        assert err <= bar and emax <= bar
     for op in ops:
         op.close()
+
+
+def test_request_follows_the_context_stream(hk, ctx):
+    # b is produced on the context stream behind a long matrix product; the
+    # request is submitted at once, so its solve must wait for that copy
+    import torch
+    P = tiny_blur(128, 128, 2.0, 7, 1, k=40, s=82, lam=1e-2, sketch=W.SKETCH_SPARSE_SIGN, zeta=5, dtype="f32")
+    op = make_operator(hk, ctx, P)
+    src = torch.tensor(P.b.astype(np.float32), device="cuda:0")
+    ref = _alone(hk, op, P, src)
+    torch.cuda.synchronize()
+    srv = hk.Server(ctx, slots=2)
+    big = torch.randn(6144, 6144, device="cuda:0")
+    b = torch.zeros_like(src)
+    x = torch.full((P.n,), float("nan"), device="cuda:0")
+    for _ in range(4):
+        big = big @ big
+        big = big / big.abs().max()
+    b.copy_(src)
+    t = _submit(srv, op, P, b, x)
+    srv.wait(t)
+    r = srv.result(t)
+    srv.close()
+    _flush(f"  status {r['status']}, equal to the solve alone: {bool(torch.equal(x, ref))}")
+    assert r["status"] == 0 and torch.equal(x, ref)
+    op.close()
 
 
 def test_admission_by_memory_budget(hk, ctx):
