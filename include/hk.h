@@ -204,6 +204,25 @@ hk_status hk_solve_create(hk_op* op, const hk_params* params, hk_solve** out);
  * x_dev: device vector, n elements of the op's dtype (written during the run). */
 hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * solve of `op` with `params`, enqueued on the context stream like
+ * hk_solve_create + hk_solve_run, but with no allocation of any kind (no
+ * hipMalloc, no event, no solve handle).  Its workspace is a static device
+ * array of HK_NOALLOC_MAX_BYTES held by the library on each device until the
+ * process ends (its address is taken when a context is created on the
+ * device).  A problem whose workspace (hk_solve_workspace_bytes) exceeds it
+ * is refused with HK_ENOMEM.  b_dev / x_dev as for hk_solve_run.  info_dev:
+ * NULL, or a device array of two int32 that receives the run's status
+ * (as hk_solve_wait) and the number of basis columns built, stream-ordered.
+ * The array keeps the previous call's contents; each call clears what must
+ * start at zero.  Calls that overlap on one device (other streams, other
+ * threads) share the array and race: the caller orders them.  Asynchronous:
+ * returns once the work is queued. */
+#define HK_NOALLOC_MAX_BYTES (128u << 20)
+hk_status hk_solve_run_noalloc(hk_op* op, const hk_params* params, const void* b_dev, void* x_dev,
+                               int32_t* info_dev);
+
 /* Wait for the last run.  Returns HK_OK, HK_BREAKDOWN, or an error. */
 hk_status hk_solve_wait(hk_solve* sv);
 

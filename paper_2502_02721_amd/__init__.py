@@ -36,7 +36,7 @@ ABI_FUNCTIONS = (
     "hk_abi_version", "hk_last_error", "hk_context_create", "hk_context_destroy",
     "hk_op_create_blur", "hk_op_create_gaussian_blur", "hk_op_create_csr", "hk_op_shape",
     "hk_op_apply", "hk_op_destroy", "hk_solve_workspace_bytes", "hk_solve_create",
-    "hk_solve_run", "hk_solve_wait", "hk_solve_info", "hk_solve_get_hessenberg",
+    "hk_solve_run", "hk_solve_run_noalloc", "hk_solve_wait", "hk_solve_info", "hk_solve_get_hessenberg",
     "hk_solve_get_pivots", "hk_solve_get_residuals", "hk_solve_get_sketches",
     "hk_solve_get_basis", "hk_solve_timing", "hk_solve_grid", "hk_solve_timing_history", "hk_solve_get_trace",
     "hk_solve_destroy", "hk_server_create", "hk_server_destroy", "hk_server_submit", "hk_server_poll",
@@ -83,6 +83,7 @@ def lib():
             "hk_solve_workspace_bytes": ([vp, C.POINTER(hk_params), C.POINTER(C.c_size_t)], st),
             "hk_solve_create": ([vp, C.POINTER(hk_params), pp], st),
             "hk_solve_run": ([vp, vp, vp], st),
+            "hk_solve_run_noalloc": ([vp, C.POINTER(hk_params), vp, vp, vp], st),
             "hk_solve_wait": ([vp], st),
             "hk_solve_info": ([vp, C.POINTER(i32)], st),
             "hk_solve_get_hessenberg": ([vp, vp, vp], st),
@@ -203,6 +204,13 @@ def hk_solve_create(op, params: hk_params) -> int:
 
 def hk_solve_run(sv, b_ptr: int, x_ptr: int) -> None:
     _check(lib().hk_solve_run(C.c_void_p(sv), C.c_void_p(b_ptr), C.c_void_p(x_ptr)))
+
+
+def hk_solve_run_noalloc(op, params: hk_params, b_ptr: int, x_ptr: int, info_ptr: int = 0) -> None:
+    """One solve on the library's static workspace (no allocation); info_ptr:
+    0, or a device int32[2] that receives (status, k_done)."""
+    _check(lib().hk_solve_run_noalloc(C.c_void_p(op), C.byref(params), C.c_void_p(b_ptr), C.c_void_p(x_ptr),
+                                      C.c_void_p(info_ptr or None)))
 
 
 def hk_solve_wait(sv) -> int:

@@ -175,6 +175,7 @@ struct ApplyArgs {
 hipError_t launch_iterate(int tb, int to, int op, int sketch, int ept, const KArgs& a, hipStream_t st);
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);   // p, bytes: multiples of 16
+hipError_t launch_solve_info(const Ctl* ctl, int32_t* info, hipStream_t st);
 hipError_t launch_small_ls(const LsArgs& a, hipStream_t st);
 hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st);
 // block sketch C = S B with S generated (hk_bsk.hip)

@@ -263,6 +263,22 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(uint4* p, size_t n16)
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256) p[i] = z;
 }
 
+// info[0] = status of the run (an aborted grid barrier is HK_EDEVICE),
+// info[1] = basis columns built
+__global__ void solve_info_kernel(const Ctl* ctl, int32_t* info)
+{
+    if (threadIdx.x == 0) {
+        info[0] = ctl->abort ? -3 : ctl->status;
+        info[1] = ctl->k_done;
+    }
+}
+
+hipError_t launch_solve_info(const Ctl* ctl, int32_t* info, hipStream_t st)
+{
+    hipLaunchKernelGGL(solve_info_kernel, dim3(1), dim3(64), 0, st, ctl, info);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st)
 {
     if (bytes == 0) return hipSuccess;

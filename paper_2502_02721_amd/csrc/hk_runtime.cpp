@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <deque>
+#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstdarg>
@@ -44,6 +45,34 @@ hk_status fail(hk_status st, const char* fmt, ...)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+}  // namespace
+
+// Workspace of hk_solve_run_noalloc: a static device array, one copy per
+// GPU, held until the process ends.  Host code never passes `scratch` itself
+// to a kernel (in host code it names a host-side stand-in); it uses the
+// device address hipGetSymbolAddress returns, taken once per device.
+constexpr size_t NOALLOC_MAX_BYTES = HK_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+bool g_scratch_done[MAX_DEVICES] = {};
+
+// Device address of this device's scratch copy (the device must be current).
+void scratch_setup(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = (e == hipSuccess) ? ptr : nullptr;
+    g_scratch_done[device] = true;
+}
 }  // namespace
 
 struct hk_context {
@@ -501,6 +530,7 @@ hk_status hk_context_create(int32_t device, void* stream, hk_context** out)
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
         c->wall_rate_khz = (unsigned long long)rate;
+    scratch_setup(device);    // the no-alloc entry point's workspace on this device
     *out = c;
     return HK_OK;
 }
@@ -990,6 +1020,43 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
     sv->runs++;
     sv->ran = true;
     sv->waited = false;
+    return HK_OK;
+}
+
+hk_status hk_solve_run_noalloc(hk_op* op, const hk_params* p_in, const void* b_dev, void* x_dev, int32_t* info_dev)
+{
+    if (!op || !p_in || !b_dev || !x_dev) return fail(HK_EINVAL, "null argument");
+    hk_context* ctx = op->ctx;
+    int rect = 0;
+    hk_params pe{};
+    Plan pl;
+    size_t need = 0;
+    hk_status st = solve_plan(op, p_in, &pe, &rect, &pl, &need);
+    if (st) return st;
+    if (need > NOALLOC_MAX_BYTES)
+        return fail(HK_ENOMEM, "the solve needs %zu workspace bytes; the static workspace holds %zu", need,
+                    NOALLOC_MAX_BYTES);
+    const int dev = ctx->device;
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (dev < 0 || dev >= MAX_DEVICES || !g_scratch_done[dev])
+            return fail(HK_EDEVICE, "no static workspace was set up for device %d", dev);
+        if (!g_scratch_ptr[dev])
+            return fail(HK_EDEVICE, "hipGetSymbolAddress of the static workspace failed: %s",
+                        hipGetErrorString(g_scratch_err[dev]));
+        base = (unsigned char*)g_scratch_ptr[dev];
+    }
+    const WsLayout w = ws_layout(op, &pe, rect, pl.G, pl.nslot);
+    hk_solve sv;                       // launch arguments only: no events, no workspace of its own
+    st = solve_bind(&sv, op, &pe, rect, pl, w, base, ctx->stream);
+    if (st) return st;
+    // the previous call's contents: clear everything before the bases (each
+    // basis column is written before it is read)
+    HIP_TRY(launch_fill_zero(base, w.L, ctx->stream));
+    st = solve_enqueue(&sv, b_dev, x_dev, ctx->stream, nullptr, nullptr, nullptr);
+    if (st) return st;
+    if (info_dev) HIP_TRY(launch_solve_info(sv.ka.ctl, info_dev, ctx->stream));
     return HK_OK;
 }
 
