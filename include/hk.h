@@ -118,6 +118,19 @@ hk_status hk_op_create_blur(hk_context* ctx, int64_t ny, int64_t nx, const doubl
 hk_status hk_op_create_gaussian_blur(hk_context* ctx, int64_t ny, int64_t nx, double sigma,
                                      int32_t radius, hk_bc bc, hk_dtype dt, hk_op** out);
 
+/* Blur with a general PSF (the motion blur of the deblurring experiment,
+ * Sec. 4.1): (A u)(y, x) = sum_{a,b=-r..r} psf[(a+r)(2r+1) + (b+r)] u(y+a, x+b),
+ * a 2-D correlation, with the boundary conditions of hk_op_create_blur.
+ * psf: host array of (2r+1)^2 doubles, row-major over a (rows), copied.  A
+ * PSF of rank one (equal to an outer product ty (x) tx to within 4 ulp of its
+ * largest entry) is stored as its two factors and takes the separable path;
+ * any other is stored as the list of its nonzero entries, at most
+ * HK_PSF_MAX_TAPS of them (more: HK_EUNSUPPORTED).  Non-finite entries:
+ * HK_ENUMERIC. */
+#define HK_PSF_MAX_TAPS 2048
+hk_status hk_op_create_blur_psf(hk_context* ctx, int64_t ny, int64_t nx, const double* psf, int32_t radius,
+                                hk_bc bc, hk_dtype dt, hk_op** out);
+
 /* Sparse operator A (m x n) in CSR form: host arrays rowptr[m+1] (int64,
  * rowptr[0] = 0, nondecreasing, rowptr[m] = nnz), col[nnz] (int32, in
  * [0, n)), val[nnz] of type dt.  All copied.  The library also builds A^T

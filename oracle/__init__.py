@@ -34,7 +34,7 @@ def build(force: bool = True) -> str:
 class _Op(C.Structure):
     _fields_ = [("kind", C.c_int), ("m", C.c_int64), ("n", C.c_int64),
                 ("ny", C.c_int64), ("nx", C.c_int64), ("radius", C.c_int32), ("bc", C.c_int32),
-                ("taps_y", C.c_void_p), ("taps_x", C.c_void_p),
+                ("taps_y", C.c_void_p), ("taps_x", C.c_void_p), ("psf", C.c_void_p),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
 
 
@@ -127,10 +127,16 @@ class Operator:
         if P.kind == "blur":
             op.kind = 0
             op.ny, op.nx, op.radius, op.bc = P.ny, P.nx, P.radius, P.bc
-            ty = np.ascontiguousarray(P.taps_y, dtype=np.float64)
-            tx = np.ascontiguousarray(P.taps_x, dtype=np.float64)
-            self._keep += [ty, tx]
-            op.taps_y, op.taps_x = _ptr(ty), _ptr(tx)
+            if getattr(P, "psf", None) is not None:
+                pf = np.ascontiguousarray(P.psf, dtype=np.float64)
+                assert pf.shape == (2 * P.radius + 1, 2 * P.radius + 1)
+                self._keep.append(pf)
+                op.psf = _ptr(pf)
+            else:
+                ty = np.ascontiguousarray(P.taps_y, dtype=np.float64)
+                tx = np.ascontiguousarray(P.taps_x, dtype=np.float64)
+                self._keep += [ty, tx]
+                op.taps_y, op.taps_x = _ptr(ty), _ptr(tx)
         else:
             op.kind = 1
             rp = np.ascontiguousarray(P.rowptr, dtype=np.int64)

@@ -200,14 +200,16 @@ int orc_sketch_dense(int kind, int64_t s, int64_t m, int zeta, uint64_t seed, ui
 /* Operators: A and A^T reached only through products (Sec. 1, eq. (1)).    */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int kind;            /* 0: separable-PSF blur, 1: CSR matrix */
+    int kind;            /* 0: blur, 1: CSR matrix */
     int64_t m, n;
-    /* blur: image ny x nx row-major, PSF p(a,b) = taps_y[a+r] * taps_x[b+r] */
+    /* blur: image ny x nx row-major, PSF p(a,b) = taps_y[a+r] * taps_x[b+r],
+     * or psf[(a+r)(2r+1) + (b+r)] when psf is not NULL (a general PSF) */
     int64_t ny, nx;
     int32_t radius;
     int32_t bc;          /* 0 zero outside, 1 half-sample reflection */
     const double* taps_y;
     const double* taps_x;
+    const double* psf;
     /* CSR */
     const int64_t* rowptr;
     const int32_t* col;
@@ -236,7 +238,8 @@ double orc_blur_pixel(const orc_op* A, const double* in, int64_t y, int64_t x)
         for (int b = -r; b <= r; ++b) {
             int64_t xx = bc_index(x + b, A->nx, A->bc);
             if (xx < 0) continue;
-            double p = A->taps_y[a + r] * A->taps_x[b + r];
+            double p = A->psf ? A->psf[(int64_t)(a + r) * (2 * r + 1) + (b + r)]
+                              : A->taps_y[a + r] * A->taps_x[b + r];
             acc += p * in[yy * A->nx + xx];
         }
     }

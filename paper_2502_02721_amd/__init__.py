@@ -34,7 +34,7 @@ HK_FLAG_TRACE = 1
 # names exported by the C ABI (checked against the header by the tests)
 ABI_FUNCTIONS = (
     "hk_abi_version", "hk_last_error", "hk_context_create", "hk_context_destroy",
-    "hk_op_create_blur", "hk_op_create_gaussian_blur", "hk_op_create_csr", "hk_op_shape",
+    "hk_op_create_blur", "hk_op_create_gaussian_blur", "hk_op_create_blur_psf", "hk_op_create_csr", "hk_op_shape",
     "hk_op_apply", "hk_op_destroy", "hk_solve_workspace_bytes", "hk_solve_create",
     "hk_solve_run", "hk_solve_run_noalloc", "hk_solve_wait", "hk_solve_info", "hk_solve_get_hessenberg",
     "hk_solve_get_pivots", "hk_solve_get_residuals", "hk_solve_get_sketches",
@@ -76,6 +76,7 @@ def lib():
             "hk_context_destroy": ([vp], st),
             "hk_op_create_blur": ([vp, i64, i64, vp, vp, i32, i32, i32, pp], st),
             "hk_op_create_gaussian_blur": ([vp, i64, i64, C.c_double, i32, i32, i32, pp], st),
+            "hk_op_create_blur_psf": ([vp, i64, i64, vp, i32, i32, i32, pp], st),
             "hk_op_create_csr": ([vp, i64, i64, i64, vp, vp, vp, i32, pp], st),
             "hk_op_shape": ([vp, C.POINTER(i64), C.POINTER(i64)], st),
             "hk_op_apply": ([vp, i32, vp, vp], st),
@@ -156,6 +157,15 @@ def hk_op_create_gaussian_blur(ctx, ny, nx, sigma, radius, bc, dtype) -> int:
     h = C.c_void_p()
     _check(lib().hk_op_create_gaussian_blur(C.c_void_p(ctx), ny, nx, sigma, radius, bc, dtype,
                                             C.byref(h)))
+    return h.value
+
+
+def hk_op_create_blur_psf(ctx, ny, nx, psf, radius, bc, dtype) -> int:
+    pf = np.ascontiguousarray(psf, dtype=np.float64)
+    if pf.shape != (2 * radius + 1, 2 * radius + 1):
+        raise ValueError("psf must be a (2*radius+1) x (2*radius+1) array")
+    h = C.c_void_p()
+    _check(lib().hk_op_create_blur_psf(C.c_void_p(ctx), ny, nx, _np_ptr(pf), radius, bc, dtype, C.byref(h)))
     return h.value
 
 
@@ -357,6 +367,10 @@ class Operator(_Owner):
     @classmethod
     def blur(cls, ctx, ny, nx, taps_y, taps_x, radius, bc, dtype):
         return cls(ctx, hk_op_create_blur(ctx.handle, ny, nx, taps_y, taps_x, radius, bc, dtype), dtype)
+
+    @classmethod
+    def blur_psf(cls, ctx, ny, nx, psf, radius, bc, dtype):
+        return cls(ctx, hk_op_create_blur_psf(ctx.handle, ny, nx, psf, radius, bc, dtype), dtype)
 
     @classmethod
     def gaussian_blur(cls, ctx, ny, nx, sigma, radius, bc, dtype):

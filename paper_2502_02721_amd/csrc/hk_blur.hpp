@@ -55,34 +55,6 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     return t;
 }
 
-// (A v)(p) for the stored vector v (global), every workgroup the same way.
-template <typename TB>
-__device__ double stencil_at(const TB* __restrict__ v, int p, int ny, int nx, int r, int bc,
-                             const double* tyl, const double* txl, double* red)
-{
-    const int py = p / nx, px = p - py * nx;
-    const int w = 2 * r + 1;
-    constexpr int SB = 4;
-    double acc = 0.0;
-    for (int o0 = 0; o0 < w * w; o0 += SB * NT) {
-        TB val[SB];
-        double wgt[SB];
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int o = o0 + u * NT + (int)threadIdx.x;
-            const int oc = o < w * w ? o : 0;
-            const int a = oc / w, b = oc - a * w;
-            const int y = bc_map(py + a - r, ny, bc), x = bc_map(px + b - r, nx, bc);
-            const bool in = o < w * w && y >= 0 && x >= 0;
-            val[u] = v[in ? y * nx + x : 0];
-            wgt[u] = in ? tyl[a] * txl[b] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < SB; ++u) acc = fma(wgt[u], (double)val[u], acc);
-    }
-    return block_sum(acc, red);
-}
-
 template <typename TB, typename TO, int SK, int EPT>
 __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
 {
@@ -132,12 +104,23 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
 
     for (int q = threadIdx.x; q < (NT * EPT + 31) / 32; q += NT) pm.bits[q] = 0u;
     if (threadIdx.x == 0) { s_cnt = 0; s_nw = 0; }
-    for (int q = threadIdx.x; q < tw; q += NT) {
-        taps[q] = a.taps_y[q];
-        taps[tw + q] = a.taps_x[q];
-    }
-    const double* tyl = taps;
-    const double* txl = taps + tw;
+    const PsfL psf = psf_stage((unsigned char*)taps, r, a.taps_y, a.taps_x, a.toff, a.tw, a.ntap);
+    const double* tyl = psf.tyl;
+    const double* txl = psf.txl;
+    // the stencil's taps: the (2r+1)^2 offsets of a separable PSF, or the
+    // list of a general one; tap_at gives offset (aa, bb) in [0, 2r] and weight
+    const int ntaps = a.ntap > 0 ? a.ntap : tw * tw;
+    auto tap_at = [&](int o, int& aa, int& bb) -> double {
+        if (a.ntap > 0) {
+            const int t = psf.toff[o];
+            aa = t >> 16;
+            bb = t & 0xffff;
+            return psf.tw[o];
+        }
+        aa = o / tw;
+        bb = o - aa * tw;
+        return tyl[aa] * txl[bb];
+    };
     if constexpr (SK == SK_SPARSE) {
         sketch_rows_build(a.spm, tm, a.s, a.zeta, 2u, a.seed_lo, a.seed_hi, rows2, (unsigned*)sk);
         if (a.lam > 0.0) sketch_rows_build(a.spm, tm, a.s, a.zeta, 1u, a.seed_lo, a.seed_hi, rows1, (unsigned*)sk);
@@ -299,7 +282,6 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         const double* wpp = a.wpart + (long long)prv * kp1 * a.nslot;
         const TB* vj = V + (long long)j * ld;
         const int py = p / nx, px = p - py * nx;
-        const int tw2 = tw * tw;
         const int tot = j * a.nslot;
         // The coefficients depend only on p_j: the row of the pivot block
         // (P(j, c) = l_c(p_j)), the window partials of A v_j left by the
@@ -321,16 +303,16 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             // (c) first batch of stencil taps at p_j
             TB sv[SBS];
-            int so[SBS];
+            double sw[SBS];
 #pragma unroll
             for (int u = 0; u < SBS; ++u) {
                 const int o = u * NT + (int)threadIdx.x;
-                const int oc = o < tw2 ? o : 0;
-                const int aa = oc / tw, bb = oc - aa * tw;
+                int aa, bb;
+                const double wgt = tap_at(o < ntaps ? o : 0, aa, bb);
                 const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
-                const bool in = o < tw2 && y >= 0 && x >= 0;
+                const bool in = o < ntaps && y >= 0 && x >= 0;
                 sv[u] = vj[in ? y * nx + x : 0];
-                so[u] = in ? oc : -1;
+                sw[u] = in ? wgt : 0.0;
             }
             middle();
             // consume
@@ -344,16 +326,13 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             for (int q = SBW * NT + (int)threadIdx.x; q < tot; q += NT) slotv[q] = wpp[q];
             double st = 0.0;
 #pragma unroll
-            for (int u = 0; u < SBS; ++u) {
-                if (so[u] >= 0) {
-                    const int aa = so[u] / tw, bb = so[u] - aa * tw;
-                    st = fma(tyl[aa] * txl[bb], (double)sv[u], st);
-                }
-            }
-            for (int o = SBS * NT + (int)threadIdx.x; o < tw2; o += NT) {
-                const int aa = o / tw, bb = o - aa * tw;
+            for (int u = 0; u < SBS; ++u)
+                if (sw[u] != 0.0) st = fma(sw[u], (double)sv[u], st);
+            for (int o = SBS * NT + (int)threadIdx.x; o < ntaps; o += NT) {
+                int aa, bb;
+                const double wgt = tap_at(o, aa, bb);
                 const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
-                if (y >= 0 && x >= 0) st = fma(tyl[aa] * txl[bb], (double)vj[y * nx + x], st);
+                if (y >= 0 && x >= 0) st = fma(wgt, (double)vj[y * nx + x], st);
             }
             const double upj = block_sum(st, s_red);         // also publishes Pl and slotv
             for (int i = threadIdx.x; i < j; i += NT) {
@@ -399,7 +378,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             const bool fsk = a.lam > 0.0 && a.stepsk;
             coef_loads([&]() {
                 mark(j, 12);
-                blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert,
+                blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert,
                                      wt, pre, pin, (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
                 mark(j, 7);
             });
@@ -436,7 +415,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             __syncthreads();
             // ---- 4. the tile: u = A l_j = s_j * blur(v_j)
             mark(j, 12);
-            blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, tyl, txl, stage, vert, wt,
+            blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert, wt,
                           (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
             mark(j, 7);
 #pragma unroll
@@ -494,7 +473,16 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 const int py = p / nx, px = p - py * nx;
                 double acc2 = 0.0;
                 const bool rect = a.bc == 0 || (py - r >= 0 && py + r < ny && px - r >= 0 && px + r < nx);
-                if (rect) {
+                if (a.ntap > 0) {
+                    // general PSF: lanes take its taps
+                    for (int t = lane; t < a.ntap; t += 64) {
+                        int aa, bb;
+                        const double wgt = tap_at(t, aa, bb);
+                        const int y = bc_map(py + aa - r, ny, a.bc), x = bc_map(px + bb - r, nx, a.bc);
+                        if (y >= tm.y0 && y < tm.y0 + TY && x >= tm.x0 && x < tm.x0 + TX)
+                            acc2 = fma(wgt, wt[(y - tm.y0) * TX + (x - tm.x0)], acc2);
+                    }
+                } else if (rect) {
                     const int ya = max(max(py - r, tm.y0), 0), yb = min(min(py + r, tm.y0 + TY - 1), ny - 1);
                     const int xa = max(max(px - r, tm.x0), 0), xb = min(min(px + r, tm.x0 + TX - 1), nx - 1);
                     // a window wider than 32 columns (r >= 16) meets a wide

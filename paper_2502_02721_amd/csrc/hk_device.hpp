@@ -372,15 +372,61 @@ __device__ __forceinline__ void blur_stage_issue(const TS* __restrict__ x, int n
     }
 }
 
+// The PSF as the kernels read it from LDS: separable taps tyl (x) txl
+// (ntap == 0), or a list of ntap entries of a general PSF, each an offset
+// (a + r, b + r) packed as (a + r) << 16 | (b + r) and its weight
+// p(a, b) (the correlation (A u)(y, x) = sum p(a, b) u(y + a, x + b)).
+struct PsfL {
+    const double* tyl;
+    const double* txl;
+    const int* toff;
+    const double* tw;
+    int ntap;
+};
+
+// Copy the PSF into LDS at `taps` (no barrier: the caller synchronises).
+__device__ __forceinline__ PsfL psf_stage(unsigned char* taps, int r, const double* taps_y, const double* taps_x,
+                                          const int* toff, const double* tw, int ntap)
+{
+    PsfL ps;
+    ps.ntap = ntap;
+    double* td = (double*)taps;
+    if (ntap > 0) {
+        int* to = (int*)(taps + ((ntap * 8 + 15) / 16) * 16);
+        for (int q = threadIdx.x; q < ntap; q += NT) {
+            td[q] = tw[q];
+            to[q] = toff[q];
+        }
+        ps.tw = td;
+        ps.toff = to;
+        ps.tyl = ps.txl = nullptr;
+    } else {
+        const int w = 2 * r + 1;
+        for (int q = threadIdx.x; q < w; q += NT) {
+            td[q] = taps_y[q];
+            td[w + q] = taps_x[q];
+        }
+        ps.tyl = td;
+        ps.txl = td + w;
+        ps.toff = nullptr;
+        ps.tw = nullptr;
+    }
+    return ps;
+}
+
 // Separable blur of one tile: wt = A x on the tile's pixels, with the halo
-// staged in LDS; v / in are the first block from blur_stage_issue.
+// staged in LDS; v / in are the first block from blur_stage_issue.  A
+// general PSF (ps.ntap > 0) takes one pass over its tap list instead of the
+// two 1-D passes.
 template <typename TS>
 __device__ __forceinline__ void blur_tile_staged(const TS* __restrict__ x, int ny, int nx, int r, int bc,
-                                                 const Tile& ti, int TY, int TX, const double* tyl,
-                                                 const double* txl, TS* stage, double* vert, double* wt,
+                                                 const Tile& ti, int TY, int TX, const PsfL& ps,
+                                                 TS* stage, double* vert, double* wt,
                                                  const TS (&v0)[BLUR_SB], unsigned in0,
                                                  unsigned long long* tmk = nullptr)
 {
+    const double* tyl = ps.tyl;
+    const double* txl = ps.txl;
     const int SW = TX + 2 * r, SH = TY + 2 * r;
     constexpr int SB = BLUR_SB;
 #pragma unroll
@@ -408,6 +454,35 @@ __device__ __forceinline__ void blur_tile_staged(const TS* __restrict__ x, int n
     }
     __syncthreads();
     if (tmk && threadIdx.x == 0) tmk[0] = wall_clock64();
+    if (ps.ntap > 0) {
+        // general PSF: each thread forms 4 consecutive rows of one column,
+        // one weight and offset (LDS broadcast) and 4 staged values per tap
+        const int ngy = (TY + 3) / 4;
+        for (int it = threadIdx.x; it < ngy * TX; it += NT) {
+            const int g = it / TX, xx = it - g * TX;
+            const int y0 = 4 * g;
+            const int y1 = min(y0 + 1, TY - 1), y2 = min(y0 + 2, TY - 1), y3 = min(y0 + 3, TY - 1);
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+            for (int t = 0; t < ps.ntap; ++t) {
+                const int o = ps.toff[t];
+                const double w = ps.tw[t];
+                const TS* src = stage + (o >> 16) * SW + xx + (o & 0xffff);
+                a0 = fma(w, (double)src[y0 * SW], a0);
+                a1 = fma(w, (double)src[y1 * SW], a1);
+                a2 = fma(w, (double)src[y2 * SW], a2);
+                a3 = fma(w, (double)src[y3 * SW], a3);
+            }
+            double* wo = wt + y0 * TX + xx;
+            wo[0] = a0;
+            if (y0 + 1 < TY) wo[TX] = a1;
+            if (y0 + 2 < TY) wo[2 * TX] = a2;
+            if (y0 + 3 < TY) wo[3 * TX] = a3;
+        }
+        __syncthreads();
+        if (tmk && threadIdx.x == 0) tmk[1] = wall_clock64();
+        return;
+    }
     const int taps = 2 * r + 1;
     // vertical pass: each thread computes 4 consecutive rows of one column
     // from a sliding window of 4 staged values (one LDS read, 4 independent
@@ -483,13 +558,13 @@ __device__ __forceinline__ void blur_tile_staged(const TS* __restrict__ x, int n
 
 template <typename TS>
 __device__ __forceinline__ void blur_tile(const TS* __restrict__ x, int ny, int nx, int r, int bc, const Tile& ti,
-                                          int TY, int TX, const double* tyl, const double* txl, TS* stage,
+                                          int TY, int TX, const PsfL& ps, TS* stage,
                                           double* vert, double* wt, unsigned long long* tmk = nullptr)
 {
     TS v[BLUR_SB];
     unsigned in;
     blur_stage_issue<TS>(x, ny, nx, r, bc, ti, TY, TX, v, in);
-    blur_tile_staged<TS>(x, ny, nx, r, bc, ti, TY, TX, tyl, txl, stage, vert, wt, v, in, tmk);
+    blur_tile_staged<TS>(x, ny, nx, r, bc, ti, TY, TX, ps, stage, vert, wt, v, in, tmk);
 }
 
 // Long rows (a wave per row): each wave takes two rows at a time and issues
@@ -1297,12 +1372,8 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
         if (rect) pn.bits[q] = 0u;
     }
     if (threadIdx.x == 0) { s_cnt_m = 0; s_cnt_n = 0; }
-    if constexpr (OP == OP_BLUR) {
-        for (int q = threadIdx.x; q < 2 * a.r + 1; q += NT) {
-            taps[q] = a.taps_y[q];
-            taps[2 * a.r + 1 + q] = a.taps_x[q];
-        }
-    }
+    PsfL psf{};
+    if constexpr (OP == OP_BLUR) psf = psf_stage((unsigned char*)taps, a.r, a.taps_y, a.taps_x, a.toff, a.tw, a.ntap);
     __syncthreads();
 
     // element ownership of this thread in the m-tile (and n-tile)
@@ -1354,8 +1425,7 @@ __global__ __launch_bounds__(NT) void iterate_kernel(KArgs a)
     }
     auto op_forward = [&](const TB* xin) {   // wt = A xin on the m-tile
         if constexpr (OP == OP_BLUR) {
-            blur_tile<TB>(xin, a.ny, a.nx, a.r, a.bc, tm, a.spm.TY, a.spm.TX, taps,
-                          taps + 2 * a.r + 1, stage, vert, wt);
+            blur_tile<TB>(xin, a.ny, a.nx, a.r, a.bc, tm, a.spm.TY, a.spm.TX, psf, stage, vert, wt);
         } else {
             csr_tile<TO, TB>(a.rp, a.ci, (const TO*)a.cv, xin, tm, a.lpr, wt, rpl_m, rb_m);
         }

@@ -81,10 +81,14 @@ struct KArgs {
     int G;                      // workgroups = tiles
     const void* b;
     Space spm, spn;             // tiling of the data space (m) and unknowns (n)
-    // blur
+    // blur: separable taps, or (ntap > 0) the tap list of a general PSF,
+    // offsets (a + r) << 16 | (b + r) and weights
     int ny, nx, r, bc;
     const double* taps_y;
     const double* taps_x;
+    const int* toff;
+    const double* tw;
+    int ntap;
     // CSR of A (m rows) and of A^T (n rows)
     const int64_t* rp;  const int* ci;  const void* cv;
     const int64_t* rpt; const int* cit; const void* cvt;
@@ -129,6 +133,13 @@ struct KArgs {
     int lds_rp_m, lds_rp_n;
 };
 
+// LDS bytes of a blur's PSF: 2 (2r + 1) separable taps, or ntap weights and
+// offsets of a general PSF
+__host__ __device__ inline int psf_lds_bytes(int r, int ntap)
+{
+    return ntap > 0 ? ((ntap * 8 + 15) / 16) * 16 + ntap * 4 : 2 * (2 * r + 1) * 8;
+}
+
 // Column-packed strict lower triangle of a (k+1) x (k+1) pivot block:
 // column c holds rows c+1..k.
 __host__ __device__ inline int packed_col(int c, int k) { return c * k - (c * (c - 1)) / 2; }
@@ -164,6 +175,7 @@ struct ApplyArgs {
     Space sp;                    // output-space tiling
     int ny, nx, r, bc;
     const double* taps_y; const double* taps_x;
+    const int* toff; const double* tw; int ntap;   // general PSF (ntap > 0)
     const int64_t* rp; const int* ci; const void* cv;
     int lpr;
     const void* x; void* y;

@@ -169,13 +169,9 @@ __global__ __launch_bounds__(NT) void apply_kernel(ApplyArgs a)
     double* taps = (double*)(smem + a.lds_taps);
     const Tile ti = tile_info(a.sp, blockIdx.x);
     if constexpr (OP == OP_BLUR) {
-        for (int q = threadIdx.x; q < 2 * a.r + 1; q += NT) {
-            taps[q] = a.taps_y[q];
-            taps[2 * a.r + 1 + q] = a.taps_x[q];
-        }
+        const PsfL psf = psf_stage((unsigned char*)taps, a.r, a.taps_y, a.taps_x, a.toff, a.tw, a.ntap);
         __syncthreads();
-        blur_tile<TS>((const TS*)a.x, a.ny, a.nx, a.r, a.bc, ti, a.sp.TY, a.sp.TX, taps,
-                      taps + 2 * a.r + 1, stage, vert, wt);
+        blur_tile<TS>((const TS*)a.x, a.ny, a.nx, a.r, a.bc, ti, a.sp.TY, a.sp.TX, psf, stage, vert, wt);
     } else {
         csr_tile<TS, TS>(a.rp, a.ci, (const TS*)a.cv, (const TS*)a.x, ti, a.lpr, wt);
     }

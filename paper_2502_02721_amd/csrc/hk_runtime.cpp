@@ -12,6 +12,7 @@
 #include <deque>
 #include <mutex>
 #include <thread>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -90,7 +91,10 @@ struct hk_op {
     int dtype = HK_F64;
     // blur
     int ny = 0, nx = 0, r = 0, bc = 0;
-    double* d_taps = nullptr;          // taps_y then taps_x
+    double* d_taps = nullptr;          // taps_y then taps_x (separable PSF)
+    int ntap = 0;                      // general PSF: its nonzero entries
+    int* d_toff = nullptr;             // (a + r) << 16 | (b + r)
+    double* d_tw = nullptr;            // p(a, b)
     // CSR
     int64_t nnz = 0;
     int64_t* d_rp = nullptr;
@@ -164,7 +168,7 @@ struct Plan {
     std::string why;
 };
 
-int lds_layout(KArgs& a, int kp1, int s, int ept, int rect, int op, int TY, int TX, int r, int dtype,
+int lds_layout(KArgs& a, int kp1, int s, int ept, int rect, int op, int TY, int TX, int r, int ntap, int dtype,
                int pmode, int rp_stage)
 {
     size_t off = 0;
@@ -193,7 +197,7 @@ int lds_layout(KArgs& a, int kp1, int s, int ept, int rect, int op, int TY, int 
         const int SW = TX + 2 * r, SH = TY + 2 * r;
         a.lds_stage = take(dsize(dtype) * (size_t)SW * SH);
         a.lds_vert = take(sizeof(double) * (size_t)TY * SW);
-        a.lds_taps = take(sizeof(double) * 2 * (2 * r + 1));
+        a.lds_taps = take(psf_lds_bytes(r, ntap));
     } else {
         a.lds_stage = a.lds_vert = a.lds_taps = 0;
     }
@@ -217,7 +221,8 @@ int spx_of(int r, int TX) { return (2 * r + 1 + TX - 1) / TX + 1; }
 int nslot_of(int r, int TY, int TX) { return spx_of(r, TX) * ((2 * r + 1 + TY - 1) / TY + 1); }
 
 // LDS of the single-barrier blur kernel; 0 if it does not fit.
-int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, int tb, int zeta, size_t lds_max)
+int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, int ntap, int tb, int zeta,
+                      size_t lds_max)
 {
     a.lds_rp_m = a.lds_rp_n = -1;
     size_t off = 0;
@@ -242,7 +247,7 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
     const int SW = TX + 2 * r, SH = TY + 2 * r;
     a.lds_stage = take(dsize(tb) * (size_t)SW * SH);
     a.lds_vert = take(sizeof(double) * (size_t)TY * SW);
-    a.lds_taps = take(sizeof(double) * 2 * (2 * r + 1));
+    a.lds_taps = take(psf_lds_bytes(r, ntap));
     a.lds_wred = take(sizeof(double) * (size_t)kp1 * (size_t)std::max(NWAVE, 1 + nslot_of(r, TY, TX)));
     a.lds_pD = take(pdsize(tb) * (size_t)packed_size(k));
     a.lds_pL = a.lds_pD;
@@ -278,7 +283,7 @@ Plan plan_solve(const hk_op* op, const hk_params* p, int rect, int max_blocks, s
     auto layout = [&](int ept, int TY, int TX, int r, int opk) {
         for (int pmode = 0; pmode < 2; ++pmode) {
             for (int rps = 1; rps >= 0; --rps) {
-                lds_layout(pl.lds, kp1_of(p), p->s, ept, rect, opk, TY, TX, r, tb, pmode, rps);
+                lds_layout(pl.lds, kp1_of(p), p->s, ept, rect, opk, TY, TX, r, op->ntap, tb, pmode, rps);
                 if ((size_t)pl.lds.lds_total <= lds_max) {
                     pl.lds_total = pl.lds.lds_total;
                     return;
@@ -310,7 +315,7 @@ Plan plan_solve(const hk_op* op, const hk_params* p, int rect, int max_blocks, s
             pl.G = G;
             pl.ept = (TY * TX + NT - 1) / NT;
             if (pl.ept > 2) pl.ept = 4;
-            if (lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, tb,
+            if (lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, op->ntap, tb,
                                   p->sketch == HK_SKETCH_SPARSE_SIGN ? p->zeta : 0, lds_max)) {
                 pl.kernel = OP_BLUR_ONEBAR;
                 pl.lds_total = pl.lds.lds_total;
@@ -546,6 +551,8 @@ static void op_free(hk_op* op)
 {
     if (!op) return;
     hipFree(op->d_taps);
+    hipFree(op->d_toff);
+    hipFree(op->d_tw);
     hipFree(op->d_rp);
     hipFree(op->d_ci);
     hipFree(op->d_cv);
@@ -609,6 +616,72 @@ hk_status hk_op_create_gaussian_blur(hk_context* ctx, int64_t ny, int64_t nx, do
     }
     for (double& v : g) v /= sum;
     return hk_op_create_blur(ctx, ny, nx, g.data(), g.data(), radius, bc, dt, out);
+}
+
+hk_status hk_op_create_blur_psf(hk_context* ctx, int64_t ny, int64_t nx, const double* psf, int32_t radius,
+                                hk_bc bc, hk_dtype dt, hk_op** out)
+{
+    if (!out) return fail(HK_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!ctx || !psf) return fail(HK_EINVAL, "null argument");
+    if (radius < 0 || radius > 64) return fail(HK_EINVAL, "radius %d outside [0, 64]", radius);
+    const int w = 2 * radius + 1;
+    double pmax = 0.0;
+    int a0 = 0, b0 = 0;
+    for (int a = 0; a < w; ++a)
+        for (int b = 0; b < w; ++b) {
+            const double v = psf[(size_t)a * w + b];
+            if (!std::isfinite(v)) return fail(HK_ENUMERIC, "non-finite PSF entry at (%d, %d)", a, b);
+            if (std::fabs(v) > pmax) { pmax = std::fabs(v); a0 = a; b0 = b; }
+        }
+    // A PSF of rank one, p(a, b) = ty(a) tx(b) to rounding, takes the
+    // separable path: ty(a) = p(a, b0) / p(a0, b0), tx(b) = p(a0, b)
+    if (pmax > 0.0) {
+        std::vector<double> ty(w), tx(w);
+        for (int a = 0; a < w; ++a) ty[a] = psf[(size_t)a * w + b0] / psf[(size_t)a0 * w + b0];
+        for (int b = 0; b < w; ++b) tx[b] = psf[(size_t)a0 * w + b];
+        bool sep = true;
+        for (int a = 0; a < w && sep; ++a)
+            for (int b = 0; b < w; ++b)
+                if (std::fabs(ty[a] * tx[b] - psf[(size_t)a * w + b]) > 4.0 * DBL_EPSILON * pmax) { sep = false; break; }
+        if (sep) return hk_op_create_blur(ctx, ny, nx, ty.data(), tx.data(), radius, bc, dt, out);
+    }
+    // the nonzero entries as a tap list
+    std::vector<int> toff;
+    std::vector<double> tw;
+    double asum = 0.0;
+    for (int a = 0; a < w; ++a)
+        for (int b = 0; b < w; ++b) {
+            const double v = psf[(size_t)a * w + b];
+            if (v == 0.0) continue;
+            toff.push_back((a << 16) | b);
+            tw.push_back(v);
+            asum += std::fabs(v);
+        }
+    if ((int)toff.size() > HK_PSF_MAX_TAPS)
+        return fail(HK_EUNSUPPORTED, "the PSF has %zu nonzero entries; at most %d are supported", toff.size(),
+                    HK_PSF_MAX_TAPS);
+    if (toff.empty()) {   // the zero operator: one zero tap keeps the list nonempty
+        toff.push_back((radius << 16) | radius);
+        tw.push_back(0.0);
+    }
+    // the separable creation checks the image, boundary and dtype; then the
+    // taps are replaced by the list
+    std::vector<double> unit(w, 0.0);
+    unit[radius] = 1.0;
+    hk_op* op = nullptr;
+    hk_status st = hk_op_create_blur(ctx, ny, nx, unit.data(), unit.data(), radius, bc, dt, &op);
+    if (st) return st;
+    op->ntap = (int)toff.size();
+    op->anorm = op->anorm_t = asum;
+    bool ok = hipMalloc(&op->d_toff, sizeof(int) * toff.size()) == hipSuccess &&
+              hipMalloc(&op->d_tw, sizeof(double) * tw.size()) == hipSuccess;
+    if (!ok) { op_free(op); return fail(HK_ENOMEM, "hipMalloc failed"); }
+    ok = hipMemcpy(op->d_toff, toff.data(), sizeof(int) * toff.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(op->d_tw, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) { op_free(op); return fail(HK_EDEVICE, "hipMemcpy failed"); }
+    *out = op;
+    return HK_OK;
 }
 
 hk_status hk_op_create_csr(hk_context* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
@@ -713,14 +786,17 @@ hk_status hk_op_apply(hk_op* op, int32_t transpose, const void* x_dev, void* y_d
         a.sp = sp;
         a.ny = op->ny; a.nx = op->nx; a.r = op->r; a.bc = op->bc;
         a.taps_y = op->d_taps;
-        a.taps_x = op->d_taps + 2 * op->r + 1;
+        a.taps_x = op->d_taps ? op->d_taps + 2 * op->r + 1 : nullptr;
+        a.toff = op->d_toff;
+        a.tw = op->d_tw;
+        a.ntap = op->ntap;
         size_t off = 0;
         auto take = [&](size_t b) { size_t o = off; off = align_up(off + b, 16); return (int)o; };
         const int SW = sp.TX + 2 * op->r, SH = sp.TY + 2 * op->r;
         a.lds_w = take(sizeof(double) * sp.TY * sp.TX);
         a.lds_stage = take(dsize(op->dtype) * (size_t)SW * SH);
         a.lds_vert = take(sizeof(double) * (size_t)sp.TY * SW);
-        a.lds_taps = take(sizeof(double) * 2 * (2 * op->r + 1));
+        a.lds_taps = take(psf_lds_bytes(op->r, op->ntap));
         a.lds_total = (int)off;
         if ((size_t)a.lds_total > op->ctx->lds_max) return fail(HK_EUNSUPPORTED, "blur radius too large for LDS");
     } else {
@@ -835,6 +911,9 @@ static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rec
     a.ny = op->ny; a.nx = op->nx; a.r = op->r; a.bc = op->bc;
     a.taps_y = op->d_taps;
     a.taps_x = op->d_taps ? op->d_taps + 2 * op->r + 1 : nullptr;
+    a.toff = op->d_toff;
+    a.tw = op->d_tw;
+    a.ntap = op->ntap;
     a.rp = op->d_rp; a.ci = op->d_ci; a.cv = op->d_cv;
     a.rpt = op->d_rpt; a.cit = op->d_cit; a.cvt = op->d_cvt;
     a.lpr = op->lpr; a.lprt = op->lprt;

@@ -39,6 +39,8 @@ def rounded_problem(P):
 def make_operator(hk, ctx, P):
     dt = hk.HK_F64 if P.dtype == "f64" else hk.HK_F32
     if P.kind == "blur":
+        if P.psf is not None:
+            return hk.Operator.blur_psf(ctx, P.ny, P.nx, P.psf, P.radius, P.bc, dt)
         return hk.Operator.blur(ctx, P.ny, P.nx, P.taps_y, P.taps_x, P.radius, P.bc, dt)
     return hk.Operator.csr(ctx, P.m, P.n, P.rowptr, P.col, P.val.astype(storage_np(P.dtype)), dt)
 

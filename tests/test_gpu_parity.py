@@ -51,6 +51,49 @@ def test_blur_apply(hk, ctx, orc, dtype, ny, nx, r, bc):
     assert np.max(np.abs(y - ref)) <= tol * np.max(np.abs(ref))
 
 
+def motion_blur(ny, nx, length, angle, r, bc, k, s, lam=0.0, sketch=W.SKETCH_SPARSE_SIGN, zeta=4, dtype="f32"):
+    """A deblurring problem under linear motion blur (a PSF of rank > 1)."""
+    return W.blur_problem(f"motion{ny}x{nx}", ny, nx, None, r, bc, "piecewise", 0.01, k=k, s=s, lam=lam,
+                          sketch=sketch, zeta=zeta, dtype=dtype, cfg_id=8, psf=W.motion_psf(length, angle, r))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ny,nx,r,bc,kind", [(64, 64, 7, W.BC_ZERO, "motion"), (50, 70, 3, W.BC_REFLECT, "random"),
+                                             (512, 512, 15, W.BC_REFLECT, "motion"),
+                                             (37, 129, 15, W.BC_ZERO, "random")])
+def test_general_psf_apply(hk, ctx, orc, dtype, ny, nx, r, bc, kind):
+    import torch
+    _flush(f"general PSF apply {ny}x{nx} r={r} bc={bc} {kind} {dtype}")
+    if kind == "motion":
+        psf = W.motion_psf(2 * r - 1, 30.0, r)
+    else:
+        psf = np.random.default_rng(9).uniform(-0.2, 1.0, (2 * r + 1, 2 * r + 1))
+    P = tiny_blur(ny, nx, 1.0, r, bc, k=1, s=2, dtype=dtype).replace(psf=psf)
+    from hk_gpu import make_operator
+    op = make_operator(hk, ctx, P)
+    x = np.random.default_rng(3).standard_normal(P.n).astype(storage_np(dtype))
+    y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+    ref = orc.Operator(P).apply(x.astype(np.float64))
+    tol = 1e-14 if dtype == "f64" else 1e-6
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    _flush(f"  max rel {err:.2e}")
+    assert err <= tol
+
+
+def test_general_psf_limits(hk, ctx):
+    from hk_gpu import make_operator
+    P = tiny_blur(64, 64, 1.0, 25, W.BC_ZERO, k=1, s=2)
+    dense = np.full((51, 51), 1.0 / 51 ** 2)
+    dense[0, 0] *= 2.0          # not of rank one: 2601 nonzero taps
+    with pytest.raises(hk.HKError) as e:
+        make_operator(hk, ctx, P.replace(psf=dense))
+    assert e.value.status == hk.HK_EUNSUPPORTED
+    bad = np.zeros((5, 5)); bad[2, 2] = np.nan
+    with pytest.raises(hk.HKError) as e:
+        make_operator(hk, ctx, tiny_blur(16, 16, 1.0, 2, W.BC_ZERO, k=1, s=2).replace(psf=bad))
+    assert e.value.status == hk.HK_ENUMERIC
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_csr_apply_and_transpose(hk, ctx, orc, dtype):
     import torch
@@ -269,6 +312,25 @@ def test_rank_deficient_small_problem(hk, ctx, orc):
     with pytest.raises(hk.HKError) as e:
         gpu_solve(hk, ctx, P, method=hk.HK_METHOD_HESSENBERG, keep_basis=False)
     assert e.value.status == hk.HK_ENUMERIC
+
+
+# ---------------------------------------------------------------- general PSF (motion blur)
+@pytest.mark.parametrize("case", ["512_f32_sparse", "ragged_f64_gauss", "ragged_f32_none", "rank1_as_2d"])
+def test_scmrh_general_psf(hk, ctx, orc, case):
+    # the deblurring experiment's motion blur (Sec. 4.1): a PSF of rank > 1
+    # through the stencil's tap list; a rank-one PSF given as a 2-D array
+    # takes the separable path
+    if case == "512_f32_sparse":
+        P = motion_blur(512, 512, 21.0, 30.0, 15, W.BC_REFLECT, k=40, s=160, lam=1e-2)
+    elif case == "ragged_f64_gauss":
+        P = motion_blur(50, 70, 9.0, 60.0, 6, W.BC_ZERO, k=25, s=60, sketch=W.SKETCH_GAUSSIAN, dtype="f64")
+    elif case == "ragged_f32_none":
+        P = motion_blur(50, 70, 9.0, 120.0, 6, W.BC_REFLECT, k=25, s=60, lam=1e-2, sketch=W.SKETCH_NONE)
+    else:
+        t = W.gaussian_taps(1.5, 5)
+        P = tiny_blur(50, 70, 1.5, 5, W.BC_REFLECT, k=25, s=60, lam=1e-2, sketch=W.SKETCH_SPARSE_SIGN, zeta=5,
+                      dtype="f64").replace(psf=np.outer(t, t))
+    _parity(hk, ctx, orc, P)
 
 
 def test_large_sketch_column_ls(hk, ctx, orc):

@@ -31,6 +31,48 @@ def test_blur_matches_scipy_correlate(orc, bc, mode, ny, nx, r):
     assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("bc,mode", [(W.BC_ZERO, "constant"), (W.BC_REFLECT, "reflect")])
+@pytest.mark.parametrize("kind,ny,nx,r", [("motion", 20, 23, 6), ("random", 9, 13, 2), ("random", 31, 31, 15)])
+def test_general_psf_matches_scipy_correlate(orc, bc, mode, kind, ny, nx, r):
+    # a PSF of full rank (random) or a motion blur at 30 degrees (rank > 1):
+    # the oracle's definitional correlation against SciPy's
+    if kind == "motion":
+        psf = W.motion_psf(2 * r - 1, 30.0, r)
+        assert np.linalg.matrix_rank(psf) > 1
+    else:
+        psf = np.random.default_rng(7).uniform(-0.5, 1.0, (2 * r + 1, 2 * r + 1))
+    P = _blur_problem(ny, nx, r, bc).replace(psf=psf, taps_y=None, taps_x=None)
+    op = orc.Operator(P)
+    img = np.random.default_rng(2).standard_normal((ny, nx))
+    got = op.apply(img.ravel()).reshape(ny, nx)
+    ref = ndimage.correlate(img, psf, mode=mode, cval=0.0)
+    assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+    # an asymmetric PSF: its operator's transpose is the correlation with the
+    # flipped PSF under the zero boundary (A^T y = sum_a,b p(a, b) y(. - a, . - b))
+    if bc == W.BC_ZERO:
+        y = np.random.default_rng(3).standard_normal((ny, nx))
+        at_y = ndimage.correlate(y, psf[::-1, ::-1], mode="constant", cval=0.0)
+        assert np.isclose(np.dot(got.ravel(), y.ravel()), np.dot(img.ravel(), at_y.ravel()), rtol=1e-12)
+
+
+def test_motion_psf_geometry():
+    # sums to one, lies on the segment, symmetric under a half turn, and is
+    # rank one (a row) only when the motion is horizontal
+    r = 7
+    p0 = W.motion_psf(9.0, 0.0, r)
+    p30 = W.motion_psf(9.0, 30.0, r)
+    assert np.isclose(p0.sum(), 1.0) and np.isclose(p30.sum(), 1.0)
+    assert np.linalg.matrix_rank(p0) == 1 and np.count_nonzero(p0.sum(axis=1)) == 1
+    assert np.linalg.matrix_rank(p30) > 1
+    assert np.allclose(p30, p30[::-1, ::-1])
+    yy, xx = np.nonzero(p30)
+    # every weight sits within one grid step (in each axis) of the segment:
+    # its distance from the line is below |cos| + |sin|
+    d = np.abs((yy - r) * np.cos(np.pi / 6) + (xx - r) * np.sin(np.pi / 6))
+    assert np.all(d < np.cos(np.pi / 6) + np.sin(np.pi / 6))
+    assert np.max(np.hypot(yy - r, xx - r)) <= 4.5 + np.sqrt(2)
+
+
 def test_blur_is_kronecker_of_1d_operators(orc):
     # separable PSF: A = A_y (x) A_x, with A_y, A_x the 1-D correlation matrices
     ny, nx, r = 7, 6, 2

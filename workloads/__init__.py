@@ -47,6 +47,30 @@ def gaussian_taps(sigma: float, radius: int) -> np.ndarray:
     return g / g.sum()
 
 
+def motion_psf(length: float, angle_deg: float, radius: int) -> np.ndarray:
+    """Linear motion blur on a (2r+1) x (2r+1) grid: a segment of `length`
+    pixels through the centre at `angle_deg` (counter-clockwise from the x
+    axis, image rows pointing down), sampled at 8 points per pixel of length,
+    each sample spread bilinearly over its four nearest grid points; the
+    array sums to one.  A PSF of rank > 1 unless the segment is axis-aligned.
+    Indexing: psf[a + r, b + r] weighs the pixel at offset (a, b) (row,
+    column) in the correlation (A u)(y, x) = sum psf[a+r, b+r] u(y+a, x+b)."""
+    w = 2 * radius + 1
+    psf = np.zeros((w, w))
+    th = np.deg2rad(angle_deg)
+    ns = max(2, int(np.ceil(8 * length)) + 1)
+    for t in np.linspace(-length / 2.0, length / 2.0, ns):
+        py, px = -t * np.sin(th) + radius, t * np.cos(th) + radius
+        y0, x0 = int(np.floor(py)), int(np.floor(px))
+        fy, fx = py - y0, px - x0
+        for dy, wy in ((0, 1.0 - fy), (1, fy)):
+            for dx, wx in ((0, 1.0 - fx), (1, fx)):
+                yy, xx = y0 + dy, x0 + dx
+                if 0 <= yy < w and 0 <= xx < w:
+                    psf[yy, xx] += wy * wx
+    return psf / psf.sum()
+
+
 def radius_for_sigma(sigma: float) -> int:
     """Stencil half-width r = round(4 sigma) - 1 (sigma 2 -> 15x15, 4 -> 31x31)."""
     return max(1, int(round(4.0 * sigma)) - 1)
@@ -185,9 +209,10 @@ def joseph_parallel_csr(N: int, n_angles: int, n_bins: int, dtype=np.float32):
 # --------------------------------------------------------------------------
 # forward model for synthesising b (library routines only)
 # --------------------------------------------------------------------------
-def blur_apply_scipy(img: np.ndarray, taps_y: np.ndarray, taps_x: np.ndarray, bc: int) -> np.ndarray:
+def blur_apply_scipy(img: np.ndarray, taps_y: np.ndarray, taps_x: np.ndarray, bc: int, psf=None) -> np.ndarray:
     from scipy import ndimage
-    psf = np.outer(taps_y, taps_x)
+    if psf is None:
+        psf = np.outer(taps_y, taps_x)
     mode = "constant" if bc == BC_ZERO else "reflect"
     return ndimage.correlate(img, psf, mode=mode, cval=0.0)
 
@@ -227,6 +252,7 @@ class Problem:
     rowptr: Optional[np.ndarray] = None
     col: Optional[np.ndarray] = None
     val: Optional[np.ndarray] = None
+    psf: Optional[np.ndarray] = None   # general (2r+1) x (2r+1) PSF (None: taps_y x taps_x)
     basis: str = ""               # storage of the Krylov bases ("" = same as dtype)
     pivot_sample: int = 0         # 0: full partial pivoting; m > 0: pivot from a sample of m rows
 
@@ -240,7 +266,9 @@ class Problem:
 
 def blur_problem(name, ny, nx, sigma, radius, bc, phantom, eta, k, s, lam, sketch,
                  zeta=8, dtype="f64", cfg_id=0, phantom_seed=PHANTOM_SEED,
-                 noise_seed=NOISE_SEED) -> Problem:
+                 noise_seed=NOISE_SEED, psf=None) -> Problem:
+    """A deblurring problem: a seeded phantom blurred by the Gaussian PSF of
+    `sigma` (or by the general `psf`, a (2r+1) x (2r+1) array) plus noise."""
     rng = np.random.default_rng(phantom_seed)
     if phantom == "blobs":
         x = phantom_blobs(ny, nx, rng)
@@ -250,13 +278,17 @@ def blur_problem(name, ny, nx, sigma, radius, bc, phantom, eta, k, s, lam, sketc
         x = rng.uniform(0.0, 1.0, size=(ny, nx))
     else:
         raise ValueError(phantom)
-    taps = gaussian_taps(sigma, radius)
-    clean = blur_apply_scipy(x, taps, taps, bc)
+    taps = gaussian_taps(sigma, radius) if sigma else None
+    if psf is not None:
+        psf = np.ascontiguousarray(psf, dtype=np.float64)
+        assert psf.shape == (2 * radius + 1, 2 * radius + 1)
+    clean = blur_apply_scipy(x, taps, taps, bc, psf=psf)
     b = add_noise(clean, eta, np.random.default_rng(noise_seed))
     return Problem(name=name, kind="blur", m=ny * nx, n=ny * nx, b=b.ravel().copy(),
                    x_true=x.ravel().copy(), k=k, s=s, lam=lam, sketch=sketch, zeta=zeta,
                    seed=SKETCH_SEED_BASE + cfg_id, dtype=dtype, ny=ny, nx=nx,
-                   taps_y=taps, taps_x=taps.copy(), radius=radius, bc=bc)
+                   taps_y=taps, taps_x=None if taps is None else taps.copy(), radius=radius, bc=bc,
+                   psf=psf)
 
 
 def csr_problem(name, N, n_angles, n_bins, eta, k, s, lam, sketch, zeta=8, dtype="f32",
