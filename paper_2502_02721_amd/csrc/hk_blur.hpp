@@ -71,7 +71,9 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
     double* vert = (double*)(smem + a.lds_vert);
     double* taps = (double*)(smem + a.lds_taps);
     using TP = typename PivotT<TB>::type;
-    TP* Pl = (TP*)(smem + a.lds_pD);
+    TP* Pl = (TP*)(smem + a.lds_pD);             // pivot block P (forward substitution)
+    double* Ml = (double*)(smem + a.lds_pD);     // or M = P^{-1} (a.pinv), rows packed
+    double* rrow = (double*)(smem + a.lds_rrow); // row j of P, FP64 (a.pinv)
     double* wred = (double*)(smem + a.lds_wred);
     int* pivs = (int*)(smem + a.lds_pl_n);       // all pivots found so far
     int* wlist = (int*)(smem + a.lds_pc_n);      // pivots whose window meets this tile
@@ -122,8 +124,10 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         return tyl[aa] * txl[bb];
     };
     if constexpr (SK == SK_SPARSE) {
-        sketch_rows_build(a.spm, tm, a.s, a.zeta, 2u, a.seed_lo, a.seed_hi, rows2, (unsigned*)sk);
-        if (a.lam > 0.0) sketch_rows_build(a.spm, tm, a.s, a.zeta, 1u, a.seed_lo, a.seed_hi, rows1, (unsigned*)sk);
+        if (a.stepsk) {
+            sketch_rows_build(a.spm, tm, a.s, a.zeta, 2u, a.seed_lo, a.seed_hi, rows2, (unsigned*)sk);
+            if (a.lam > 0.0) sketch_rows_build(a.spm, tm, a.s, a.zeta, 1u, a.seed_lo, a.seed_hi, rows1, (unsigned*)sk);
+        }
     }
 
     int gm[EPT];
@@ -197,8 +201,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         // here and overlap the pivot search
         TB pre[BLUR_SB];
         unsigned pin = 0u;
-        if constexpr (SK == SK_SPARSE)
-            blur_stage_issue<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, pre, pin);
+        blur_stage_issue<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, pre, pin);
         mark(j, 0);
         {
             const int r0 = (int)(((long long)tile * a.s) / G), r1 = (int)(((long long)(tile + 1) * a.s) / G);
@@ -316,8 +319,10 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             middle();
             // consume
-            if ((int)threadIdx.x < j)
-                Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TP)(sc_l[threadIdx.x] * (double)gv);
+            if ((int)threadIdx.x < j) {
+                if (a.pinv) rrow[threadIdx.x] = sc_l[threadIdx.x] * (double)gv;
+                else Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TP)(sc_l[threadIdx.x] * (double)gv);
+            }
 #pragma unroll
             for (int u = 0; u < SBW; ++u) {
                 const int q = u * NT + (int)threadIdx.x;
@@ -358,6 +363,71 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 for (int i = threadIdx.x; i <= j; i += 64) a.H[(long long)j * kp1 + i] = h_l[i];
             mark(j, 6);
         };
+        // All waves: h = P_j^{-1} u(p) from M = P_{j-1}^{-1}, kept in LDS and
+        // extended by one row per step.  With r = P(j, 0:j-1) (rrow):
+        //   h_i = u_i + sum_{c<i} M(i, c) u_c           (i < j)
+        //   M(j, c) = -(r_c + sum_{c<i<j} r_i M(i, c))   (c < j)
+        //   h_j = u_j - sum_{c<j} r_c h_c
+        // Four lanes share each output (strided partial sums, then a quad
+        // reduction), so the chain is about j/4 FMAs instead of the j
+        // dependent steps of a substitution.  Ends with h_l, hs_l and column
+        // j of H written and the workgroup synchronised.
+        auto coef_solve_pinv = [&]() {
+            mark(j, 5);
+            const int q4 = threadIdx.x & 3;
+            constexpr int UB = 8;       // loads issued before their products
+            for (int t = (int)threadIdx.x >> 2; t < 2 * j; t += NT / 4) {
+                double sacc = 0.0;
+                if (t < j) {
+                    const double* mr = Ml + (t * (t - 1)) / 2;
+                    for (int c0 = q4; c0 < t; c0 += 4 * UB) {
+                        double mv[UB], uv[UB];
+#pragma unroll
+                        for (int u = 0; u < UB; ++u) {
+                            const int c = min(c0 + 4 * u, t - 1);
+                            mv[u] = mr[c];
+                            uv[u] = pv[c];
+                        }
+#pragma unroll
+                        for (int u = 0; u < UB; ++u)
+                            if (c0 + 4 * u < t) sacc = fma(mv[u], uv[u], sacc);
+                    }
+                } else {
+                    const int c = t - j;
+                    for (int i0 = c + 1 + q4; i0 < j; i0 += 4 * UB) {
+                        double rv[UB], mv[UB];
+#pragma unroll
+                        for (int u = 0; u < UB; ++u) {
+                            const int i = min(i0 + 4 * u, j - 1);
+                            rv[u] = rrow[i];
+                            mv[u] = Ml[(i * (i - 1)) / 2 + c];
+                        }
+#pragma unroll
+                        for (int u = 0; u < UB; ++u)
+                            if (i0 + 4 * u < j) sacc = fma(rv[u], mv[u], sacc);
+                    }
+                }
+                sacc += __shfl_xor(sacc, 1);
+                sacc += __shfl_xor(sacc, 2);
+                if (q4 == 0) {
+                    if (t < j) h_l[t] = pv[t] + sacc;
+                    else Ml[(j * (j - 1)) / 2 + (t - j)] = -(rrow[t - j] + sacc);
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                double sacc = 0.0;
+                for (int c = threadIdx.x; c < j; c += 64) sacc = fma(rrow[c], h_l[c], sacc);
+                sacc = wave_sum(sacc);
+                if (threadIdx.x == 0) h_l[j] = pv[j] - sacc;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i <= j; i += NT) hs_l[i] = h_l[i] * sc_l[i];
+            if (tile == 0)
+                for (int i = threadIdx.x; i <= j; i += NT) a.H[(long long)j * kp1 + i] = h_l[i];
+            mark(j, 6);
+            __syncthreads();
+        };
         auto c_sketch = [&]() {   // c = S2 b: b itself when the basis type is narrower
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
                 const int yy = e / TX, xx = e - yy * TX;
@@ -370,28 +440,33 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             __syncthreads();
         };
+        // ---- 4. the tile: u = A l_j = s_j * blur(v_j), with the coefficient
+        //         loads in flight; then h; then (per-step sketches only) the
+        //         sketches of u and of v_j
         double acc[EPT];
-        if constexpr (SK == SK_SPARSE) {
-            // ---- 4. the tile: u = A l_j = s_j * blur(v_j), with the
-            //         coefficient loads in flight; then the sketches of u
-            //         and of v_j run on waves 1..7 while wave 0 forms h
-            const bool fsk = a.lam > 0.0 && a.stepsk;
-            coef_loads([&]() {
-                mark(j, 12);
-                blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert,
-                                     wt, pre, pin, (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
-                mark(j, 7);
-            });
+        const bool fsk = a.lam > 0.0 && a.stepsk;
+        coef_loads([&]() {
+            mark(j, 12);
+            blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert,
+                                 wt, pre, pin, (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
+            mark(j, 7);
+        });
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
+        for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
+        if (a.stepsk) {
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
                 wt[e] *= sj;
-                if (fsk) {   // S1 v_j input (the vertical-pass buffer is free now)
+                if (SK == SK_SPARSE && fsk) {   // S1 v_j input (the vertical-pass buffer is free now)
                     const int yy = e / TX, xx = e - yy * TX;
                     vert[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
                 }
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        if (a.pinv) {
+            coef_solve_pinv();
+        } else if constexpr (SK == SK_SPARSE) {
+            // wave 0 forms h while waves 1..7 form the sketch partials
             if (threadIdx.x < 64) {
                 coef_solve_wave();
             } else if (a.stepsk) {
@@ -402,33 +477,23 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                     sketch_rows_sum(vert, rows1, a.s, (double*)(a.fpart + par * GS + (long long)tile * a.s),
                                     (int)threadIdx.x - 64, NT - 64);
             }
-            __syncthreads();
-            mark(j, 15);
+        } else {
+            if (threadIdx.x < 64) coef_solve_wave();
+        }
+        __syncthreads();
+        mark(j, 15);
+        if constexpr (SK == SK_SPARSE) {
             if (j == 0 && a.stepsk) {
                 c_sketch();
                 sketch_rows_partial(wt, rows2, a.s, (double*)(a.cpart + (long long)tile * a.s));
             }
-        } else {
-            coef_loads([]() {});
-            __syncthreads();
-            if (threadIdx.x < 64) coef_solve_wave();
-            __syncthreads();
-            // ---- 4. the tile: u = A l_j = s_j * blur(v_j)
-            mark(j, 12);
-            blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert, wt,
-                          (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
-            mark(j, 7);
-#pragma unroll
-            for (int i = 0; i < EPT; ++i) acc[i] = ((vm >> i) & 1u) ? sj * wt[threadIdx.x + i * NT] : 0.0;
-            for (int e = threadIdx.x; e < TY * TX; e += NT) wt[e] *= sj;
-            __syncthreads();
-            if (a.stepsk) sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart + par * GS, tile);   // z_j
-            mark(j, 15);
-            if (j == 0 && a.stepsk) {
+        } else if (a.stepsk) {
+            sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart + par * GS, tile);   // z_j
+            if (j == 0) {
                 c_sketch();
                 sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
             }
-            if (a.lam > 0.0 && a.stepsk) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
+            if (a.lam > 0.0) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
                 for (int e = threadIdx.x; e < TY * TX; e += NT) {
                     const int yy = e / TX, xx = e - yy * TX;
                     wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];

@@ -127,6 +127,9 @@ struct KArgs {
     int nslot, spx;             // slots per pivot, slots per row of the window box
     int lds_scale, lds_hs, lds_wred;
     int lds_skt;                // sparse-sign tables (0: built on the fly)
+    // coefficients from M = P^{-1} (FP64, rows packed, extended by one row per
+    // step) instead of a forward substitution on P; row j of P in FP64
+    int pinv, lds_rrow;
     // CSR operators: the row pointers of the workgroup's m-tile and n-tile
     // rows, relative to the tile's first entry (int32), staged once per solve
     // (-1: not staged, read from global memory)

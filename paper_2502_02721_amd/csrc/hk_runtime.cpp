@@ -220,9 +220,11 @@ int kp1_of(const hk_params* p) { return p->k + 1; }
 int spx_of(int r, int TX) { return (2 * r + 1 + TX - 1) / TX + 1; }
 int nslot_of(int r, int TY, int TX) { return spx_of(r, TX) * ((2 * r + 1 + TY - 1) / TY + 1); }
 
-// LDS of the single-barrier blur kernel; 0 if it does not fit.
+// LDS of the single-barrier blur kernel; 0 if it does not fit.  zeta > 0:
+// the per-step sparse-sign row lists; pinv: M = P^{-1} in FP64 (else P in
+// the pivot-block type).
 int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, int ntap, int tb, int zeta,
-                      size_t lds_max)
+                      int pinv, size_t lds_max)
 {
     a.lds_rp_m = a.lds_rp_n = -1;
     size_t off = 0;
@@ -249,8 +251,10 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
     a.lds_vert = take(sizeof(double) * (size_t)TY * SW);
     a.lds_taps = take(psf_lds_bytes(r, ntap));
     a.lds_wred = take(sizeof(double) * (size_t)kp1 * (size_t)std::max(NWAVE, 1 + nslot_of(r, TY, TX)));
-    a.lds_pD = take(pdsize(tb) * (size_t)packed_size(k));
+    a.pinv = pinv;
+    a.lds_pD = take((pinv ? sizeof(double) : pdsize(tb)) * (size_t)packed_size(k));
     a.lds_pL = a.lds_pD;
+    a.lds_rrow = pinv ? take(sizeof(double) * (size_t)kp1) : 0;
     a.pmode = 0;
     a.lds_skt = 0;
     if (zeta > 0) {
@@ -262,6 +266,14 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
     if (off > lds_max) return 0;
     a.lds_total = (int)off;
     return a.lds_total;
+}
+
+// Sketch partials every step: sparse sign, and Gaussian with 16-bit bases
+// (FP64 and FP32 bases take the Gaussian sketch at the end of the solve).
+bool per_step_sketch(const hk_params* p)
+{
+    if (p->sketch == HK_SKETCH_SPARSE_SIGN) return true;
+    return p->sketch == HK_SKETCH_GAUSSIAN && (p->basis_dtype == HK_BF16 || p->basis_dtype == HK_F16);
 }
 
 Space range_space(int64_t len, int G)
@@ -315,8 +327,15 @@ Plan plan_solve(const hk_op* op, const hk_params* p, int rect, int max_blocks, s
             pl.G = G;
             pl.ept = (TY * TX + NT - 1) / NT;
             if (pl.ept > 2) pl.ept = 4;
-            if (lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, op->ntap, tb,
-                                  p->sketch == HK_SKETCH_SPARSE_SIGN ? p->zeta : 0, lds_max)) {
+            const int tabs = p->sketch == HK_SKETCH_SPARSE_SIGN ? p->zeta : 0;   // sparse-sign row lists
+            // Coefficients from M = P^{-1} (all waves, about j/4 dependent
+            // products) where no per-step sketch runs beside the
+            // substitution on wave 0, and for FP32 bases only: for FP64
+            // bases the substitution keeps the elimination's own order of
+            // operations, the closest to the sequential elimination.
+            const int pinv = (tb == HK_F32 && !per_step_sketch(p)) ? 1 : 0;
+            if ((pinv && lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, op->ntap, tb, tabs, 1, lds_max)) ||
+                lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, op->ntap, tb, tabs, 0, lds_max)) {
                 pl.kernel = OP_BLUR_ONEBAR;
                 pl.lds_total = pl.lds.lds_total;
                 pl.spx = spx_of(op->r, TX);
