@@ -158,6 +158,55 @@ def serving(hk, ctx, n: int, rate: float, slots: int):
                    "1024 px deblurring exceeds the single-kernel tile plan and is left out"}
 
 
+def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int):
+    """Several right-hand sides on the 512 x 512 deblurring operator solved
+    together (hk_params.nrhs): the workload's operator and settings with a
+    Gaussian sketch of s = 400 (its block contraction covers all the bases),
+    right-hand sides from workloads.blur_rhs_family.  Reports Hessenberg
+    iterations per second summed over the right-hand sides and the basis
+    kernel's algorithmic bandwidth (nrhs times one solve's bytes)."""
+    import torch
+    import workloads as W
+    P = W.config("c2").replace(sketch=W.SKETCH_GAUSSIAN)
+    out = {}
+    for nr in sorted({1, nrhs}):
+        probs = W.blur_rhs_family(P, nr)
+        op = hk.Operator.blur(ctx, P.ny, P.nx, P.taps_y, P.taps_x, P.radius, P.bc, hk.HK_F32)
+        sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, basis_dtype=hk.HK_F32, nrhs=nr)
+        b = torch.tensor(np.stack([Q.b.astype(np.float32) for Q in probs]), device="cuda:0")
+        x = torch.empty((nr, P.n), dtype=torch.float32, device="cuda:0")
+        for _ in range(warmup):
+            sv.run(b, x)
+        sv.wait()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sv.run(b, x)
+        st = sv.wait()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        it_ms, tot_ms = sv.timing_history(steps)
+        kd = 0
+        for r in range(nr):
+            sv.select(r)
+            kd += sv.k_done()
+        alg = nr * algorithmic_bytes(P.n, P.k, 4)
+        iter_avg = float(np.mean(it_ms))
+        achieved = alg / (iter_avg * 1e-3) / 1e9
+        out[str(nr)] = {"status": st, "ms_per_solve": round(wall * 1e3 / steps, 4),
+                        "hessenberg_iters_per_s": round(kd * steps / wall, 1),
+                        "basis_kernel_ms": round(iter_avg, 4), "total_ms": round(float(np.mean(tot_ms)), 4),
+                        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                                     "alg_bytes_per_launch": alg, "basis_bytes": nr * P.n * (P.k + 1) * 4}}
+        sv.close()
+        op.close()
+        print(f"# multi-rhs {nr}: {out[str(nr)]['ms_per_solve']} ms per solve", file=sys.stderr, flush=True)
+    return {"workload": "deblur-512x512 operator, k=100, Gaussian s=400, lambda=1e-2, FP32 bases; "
+                        f"{nrhs} right-hand sides solved together vs one",
+            "runs": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +217,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--workload", default="c2", help=argparse.SUPPRESS)
+    ap.add_argument("--rhs", type=int, default=4, help="right-hand sides of the multi-right-hand-side line (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run only a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -248,6 +298,8 @@ def main():
                        "p99": round(float(np.percentile(tot_ms, 99)), 4)},
         "roofline": roof,
     }
+    if args.rhs > 0:
+        out["multi_rhs"] = multi_rhs(hk, ctx, args.rhs, max(3, args.steps // 2), 2)
     if args.serve_requests > 0:
         out["serving"] = serving(hk, ctx, args.serve_requests, args.serve_rate, args.serve_slots)
     if not args.no_cpu_baseline:

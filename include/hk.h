@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define HK_ABI_VERSION 1
+#define HK_ABI_VERSION 2
 
 typedef int32_t hk_status;
 enum {
@@ -189,7 +189,19 @@ hk_status hk_op_destroy(hk_op* op);
  *   max_workgroups  0: the basis kernel takes one workgroup per compute
  *           unit; > 0: at most that many (larger tiles), so that several
  *           solves fit on the device side by side; a problem that needs
- *           more tiles than allowed is refused with HK_EUNSUPPORTED. */
+ *           more tiles than allowed is refused with HK_EUNSUPPORTED.
+ *   nrhs    right-hand sides solved together on the operator, 1..8 (0 means
+ *           1).  Each has its own Krylov basis, pivots, H and small problem,
+ *           computed exactly as its solve alone (same sketch S), so its
+ *           results equal the single-right-hand-side solve's bit for bit;
+ *           the right-hand sides share the basis kernel's grid barriers and
+ *           argmax round trips, and with a Gaussian sketch the sketches of
+ *           all their bases are one block contraction in which every entry
+ *           of S is generated once per 64 columns.  The multi-right-hand-side
+ *           basis is limited to blur operators with FP64 or FP32 bases and
+ *           full partial pivoting, and to a k and a count whose per-right-
+ *           hand-side state fits the kernel's LDS (HK_EUNSUPPORTED
+ *           otherwise).  See hk_solve_run and hk_solve_select_rhs. */
 typedef struct {
     int32_t k;
     int32_t s;
@@ -202,6 +214,7 @@ typedef struct {
     uint32_t flags;
     int32_t pivot_sample;
     int32_t max_workgroups;
+    int32_t nrhs;
 } hk_params;
 
 /* Device workspace a solve of `op` with `params` holds (bases, Hessenberg
@@ -213,8 +226,9 @@ hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* params, siz
 hk_status hk_solve_create(hk_op* op, const hk_params* params, hk_solve** out);
 
 /* Run: enqueue the whole solve on the context stream and return at once.
- * b_dev: device vector, m elements of the op's dtype (read during the run).
- * x_dev: device vector, n elements of the op's dtype (written during the run). */
+ * b_dev: device array of the op's dtype, m x nrhs column-major (right-hand
+ * side r at b_dev + r m; read during the run).  x_dev: n x nrhs likewise
+ * (written during the run). */
 hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -236,7 +250,9 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev);
 hk_status hk_solve_run_noalloc(hk_op* op, const hk_params* params, const void* b_dev, void* x_dev,
                                int32_t* info_dev);
 
-/* Wait for the last run.  Returns HK_OK, HK_BREAKDOWN, or an error. */
+/* Wait for the last run.  Returns HK_OK, HK_BREAKDOWN, or an error.  With
+ * several right-hand sides: an error of any of them (the first), else
+ * HK_BREAKDOWN if any broke down, else HK_OK. */
 hk_status hk_solve_wait(hk_solve* sv);
 
 /* Results of the last run (each call waits for it first).
@@ -260,6 +276,11 @@ hk_status hk_solve_wait(hk_solve* sv);
  *               then returns l_j rounded to basis_dtype a second time.  For
  *               the other kernels which = 2 equals which = 0. */
 hk_status hk_solve_info(hk_solve* sv, int32_t* k_done);
+
+/* The right-hand side (0 .. nrhs-1) whose results hk_solve_info and the
+ * getters report from now on (0 after creation); hk_solve_info then
+ * returns that right-hand side's own status. */
+hk_status hk_solve_select_rhs(hk_solve* sv, int32_t rhs);
 hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W);
 hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g);
 hk_status hk_solve_get_residuals(hk_solve* sv, double* res);

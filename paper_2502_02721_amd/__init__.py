@@ -36,7 +36,8 @@ ABI_FUNCTIONS = (
     "hk_abi_version", "hk_last_error", "hk_context_create", "hk_context_destroy",
     "hk_op_create_blur", "hk_op_create_gaussian_blur", "hk_op_create_blur_psf", "hk_op_create_csr", "hk_op_shape",
     "hk_op_apply", "hk_op_destroy", "hk_solve_workspace_bytes", "hk_solve_create",
-    "hk_solve_run", "hk_solve_run_noalloc", "hk_solve_wait", "hk_solve_info", "hk_solve_get_hessenberg",
+    "hk_solve_run", "hk_solve_run_noalloc", "hk_solve_wait", "hk_solve_info", "hk_solve_select_rhs",
+    "hk_solve_get_hessenberg",
     "hk_solve_get_pivots", "hk_solve_get_residuals", "hk_solve_get_sketches",
     "hk_solve_get_basis", "hk_solve_timing", "hk_solve_grid", "hk_solve_timing_history", "hk_solve_get_trace",
     "hk_solve_destroy", "hk_server_create", "hk_server_destroy", "hk_server_submit", "hk_server_poll",
@@ -54,7 +55,7 @@ class hk_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("s", C.c_int32), ("lambda_", C.c_double),
                 ("sketch", C.c_int32), ("zeta", C.c_int32), ("seed", C.c_uint64),
                 ("method", C.c_int32), ("basis_dtype", C.c_int32), ("flags", C.c_uint32),
-                ("pivot_sample", C.c_int32), ("max_workgroups", C.c_int32)]
+                ("pivot_sample", C.c_int32), ("max_workgroups", C.c_int32), ("nrhs", C.c_int32)]
 
 
 _lib = None
@@ -87,6 +88,7 @@ def lib():
             "hk_solve_run_noalloc": ([vp, C.POINTER(hk_params), vp, vp, vp], st),
             "hk_solve_wait": ([vp], st),
             "hk_solve_info": ([vp, C.POINTER(i32)], st),
+            "hk_solve_select_rhs": ([vp, i32], st),
             "hk_solve_get_hessenberg": ([vp, vp, vp], st),
             "hk_solve_get_pivots": ([vp, vp, vp], st),
             "hk_solve_get_residuals": ([vp, vp], st),
@@ -194,10 +196,10 @@ def hk_op_destroy(op) -> None:
 
 
 def make_params(k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0, method=HK_METHOD_AUTO,
-                basis_dtype=HK_F64, flags=0, pivot_sample=0, max_workgroups=0) -> hk_params:
+                basis_dtype=HK_F64, flags=0, pivot_sample=0, max_workgroups=0, nrhs=1) -> hk_params:
     return hk_params(k=k, s=s, lambda_=lam, sketch=sketch, zeta=zeta, seed=seed, method=method,
                      basis_dtype=basis_dtype, flags=flags, pivot_sample=pivot_sample,
-                     max_workgroups=max_workgroups)
+                     max_workgroups=max_workgroups, nrhs=nrhs)
 
 
 def hk_solve_workspace_bytes(op, params: hk_params) -> int:
@@ -231,6 +233,10 @@ def hk_solve_info(sv) -> int:
     k = C.c_int32()
     _check(lib().hk_solve_info(C.c_void_p(sv), C.byref(k)), allow_breakdown=True)
     return k.value
+
+
+def hk_solve_select_rhs(sv, rhs: int) -> None:
+    _check(lib().hk_solve_select_rhs(C.c_void_p(sv), rhs))
 
 
 def hk_solve_get_hessenberg(sv, k: int, rect: bool):
@@ -407,13 +413,14 @@ class Solve(_Owner):
     """A solve of one operator with fixed parameters; run() may be called repeatedly."""
 
     def __init__(self, op: Operator, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
-                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0, pivot_sample=0, max_workgroups=0):
+                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0, pivot_sample=0, max_workgroups=0, nrhs=1):
         self.op = op
         if basis_dtype is None:
             basis_dtype = op.dtype
         self.basis_dtype = basis_dtype
+        self.nrhs = max(1, nrhs)
         self.params = make_params(k, s, lam, sketch, zeta, seed, method, basis_dtype, flags, pivot_sample,
-                                  max_workgroups)
+                                  max_workgroups, nrhs)
         # without a sketch the small problem is H_{k+1,k}: s is taken as k + 1
         self.k, self.s = k, (k + 1 if sketch == HK_SKETCH_NONE else s)
         self.rect = (method == HK_METHOD_CHANGING_HESSENBERG) or (method == HK_METHOD_AUTO and op.m != op.n)
@@ -427,11 +434,13 @@ class Solve(_Owner):
         return hk_solve_workspace_bytes(self.op.handle, self.params)
 
     def run(self, b, x=None):
+        """b: m elements (or nrhs x m, one right-hand side per row); x likewise with n."""
         torch = _torch()
-        self.op._vec(b, self.op.m, "b")
+        self.op._vec(b, self.op.m * self.nrhs, "b")
         if x is None:
-            x = torch.empty(self.op.n, dtype=self.op.torch_dtype(), device=b.device)
-        self.op._vec(x, self.op.n, "x")
+            shape = (self.nrhs, self.op.n) if self.nrhs > 1 else (self.op.n,)
+            x = torch.empty(shape, dtype=self.op.torch_dtype(), device=b.device)
+        self.op._vec(x, self.op.n * self.nrhs, "x")
         hk_solve_run(self.handle, b.data_ptr(), x.data_ptr())
         self._b, self._x = b, x   # keep alive until the run completes
         return x
@@ -441,6 +450,10 @@ class Solve(_Owner):
 
     def k_done(self) -> int:
         return hk_solve_info(self.handle)
+
+    def select(self, rhs: int) -> None:
+        """Report right-hand side `rhs` from now on (getters, k_done)."""
+        hk_solve_select_rhs(self.handle, rhs)
 
     def hessenberg(self):
         return hk_solve_get_hessenberg(self.handle, self.k, self.rect)

@@ -55,28 +55,55 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     return t;
 }
 
+// Several right-hand sides of one operator (a.nrhs, at most RMAX) advance in
+// lock step: each has its own basis, pivots, coefficients and sketches (its
+// workspace region, a.rhs_stride bytes apart, and its LDS block, a.lds_rhs
+// bytes apart; the bases lie side by side, (k + 1) columns each), computed
+// exactly as a single solve would; they share the grid barrier of each step
+// (the first region's control block) and the argmax round trip.
 template <typename TB, typename TO, int SK, int EPT>
-__global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
+__global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_cnt;
+    const KArgs& a = a0;
+    __shared__ int s_cnt[RMAX];
+    __shared__ int s_done[RMAX];                  // a right-hand side that has finished
     __shared__ double s_red[NWAVE];
+    const int nrhs = a0.nrhs;
+    // the workspace of right-hand side b: its region and basis (only these
+    // pointers differ between right-hand sides)
+    struct RhsP {
+        double* H; int* tp; double* amv; int* ami;
+        long long* zpart; long long* fpart; long long* cpart;
+        double* Z; double* F; double* c; Ctl* ctl; double* scale; double* wpart; double* sval; int* sidx;
+        void* L; const void* b;
+    };
+    auto rhs = [&](int b) -> RhsP {
+        const long long st = (long long)b * a0.rhs_stride;
+        auto sh = [&](auto* q) { return (decltype(q))((char*)q + st); };
+        RhsP r;
+        r.H = sh(a0.H); r.tp = sh(a0.tp); r.amv = sh(a0.amv); r.ami = sh(a0.ami);
+        r.zpart = sh(a0.zpart); r.fpart = sh(a0.fpart); r.cpart = sh(a0.cpart);
+        r.Z = sh(a0.Z); r.F = sh(a0.F); r.c = sh(a0.c); r.ctl = sh(a0.ctl);
+        r.scale = sh(a0.scale); r.wpart = sh(a0.wpart); r.sval = sh(a0.sval); r.sidx = sh(a0.sidx);
+        r.L = (void*)((TB*)a0.L + (long long)b * (a0.k + 1) * a0.ldl);
+        r.b = (const void*)((const TO*)a0.b + (long long)b * a0.m);
+        return r;
+    };
     double* h_l = (double*)(smem + a.lds_h);
     double* hs_l = (double*)(smem + a.lds_hs);
-    double* sc_l = (double*)(smem + a.lds_scale);            // s_j = 1 / eta_j
-    double* scf_l = sc_l + (KMAX + 1);                       // fixed-point scale of f_j
     double* wt = (double*)(smem + a.lds_w);
     unsigned char* sk = smem + a.lds_sk;
     TB* stage = (TB*)(smem + a.lds_stage);
     double* vert = (double*)(smem + a.lds_vert);
     double* taps = (double*)(smem + a.lds_taps);
     using TP = typename PivotT<TB>::type;
-    TP* Pl = (TP*)(smem + a.lds_pD);             // pivot block P (forward substitution)
-    double* Ml = (double*)(smem + a.lds_pD);     // or M = P^{-1} (a.pinv), rows packed
-    double* rrow = (double*)(smem + a.lds_rrow); // row j of P, FP64 (a.pinv)
     double* wred = (double*)(smem + a.lds_wred);
-    int* pivs = (int*)(smem + a.lds_pl_n);       // all pivots found so far
-    int* wlist = (int*)(smem + a.lds_pc_n);      // pivots whose window meets this tile
+    // Per right-hand side (bound in its step): the scales s_j = 1 / eta_j
+    // and fixed-point scales of f_j (lds_scale), the pivot block P (lds_pD), all pivots (lds_pl_n), the pivots whose window
+    // meets this tile (lds_pc_n) and this tile's pivots (lds_pl_m, lds_pc_m,
+    // lds_bm_m); right-hand side b's copy lies a.lds_rhs bytes further on
+    auto lds_at = [&](int off, int b) { return smem + off + b * a0.lds_rhs; };
     // sparse-sign row lists of S2 and S1 over this tile's elements
     SkRows rows2{}, rows1{};
     if constexpr (SK == SK_SPARSE) {
@@ -87,9 +114,9 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         rows2.ents = (unsigned short*)(ob + 2 * (a.s + 1));
         rows1.ents = rows2.ents + ne;
     }
-    __shared__ int s_nw;                          // length of wlist
-    __shared__ double s_amv;                      // global argmax of the phase
-    __shared__ int s_ami;
+    __shared__ int s_nw[RMAX];                    // length of wlist
+    __shared__ double s_amv[RMAX];                // global argmax of the phase
+    __shared__ int s_ami[RMAX];
 
     const int G = a.G;
     const int tile = tile_of_block(G, a.xcd_map);
@@ -100,12 +127,14 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
     Ctl* ctl = a.ctl;
     BarState bs;
 
-    PivState pm{(int*)(smem + a.lds_pl_m), (int*)(smem + a.lds_pc_m), (unsigned*)(smem + a.lds_bm_m), &s_cnt};
     const Tile tm = tile_info(a.spm, tile);
     const int tyi = tile / a.spm.ntx, txi = tile - tyi * a.spm.ntx;
 
-    for (int q = threadIdx.x; q < (NT * EPT + 31) / 32; q += NT) pm.bits[q] = 0u;
-    if (threadIdx.x == 0) { s_cnt = 0; s_nw = 0; }
+    for (int b = 0; b < nrhs; ++b) {
+        unsigned* bits = (unsigned*)lds_at(a.lds_bm_m, b);
+        for (int q = threadIdx.x; q < (NT * EPT + 31) / 32; q += NT) bits[q] = 0u;
+    }
+    if (threadIdx.x < RMAX) { s_cnt[threadIdx.x] = 0; s_nw[threadIdx.x] = 0; s_done[threadIdx.x] = 0; }
     const PsfL psf = psf_stage((unsigned char*)taps, r, a.taps_y, a.taps_x, a.toff, a.tw, a.ntap);
     const double* tyl = psf.tyl;
     const double* txl = psf.txl;
@@ -138,35 +167,32 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         if (elem_global(a.spm, tm, threadIdx.x + i * NT, g)) vm |= 1u << i; else g = 0;
         gm[i] = g;
     }
-    TB* V = (TB*)a.L;
     const long long ld = a.ldl;
-    const TO* bvec = (const TO*)a.b;
     const double inv_sk = (SK == SK_SPARSE) ? 1.0 / sqrt((double)a.zeta) : 1.0 / sqrt((double)a.s);
     const long long GS = (long long)G * a.s;
 
-    // sub-phase timestamps of workgroup 0 (tracing only): after the barrier
-    // timestamps, 16 slots per step
+    // sub-phase timestamps of workgroup 0 (tracing only; the first
+    // right-hand side): after the barrier timestamps, 16 slots per step
     unsigned long long* marks = a.trace ? a.trace + 2 * (kp1 + 2) : nullptr;
+    int cur_b = 0;
     auto mark = [&](int j, int id) {
-        if (marks && tile == 0 && threadIdx.x == 0 && (2 * (kp1 + 2) + j * 16 + id) < a.trace_cap)
+        if (marks && cur_b == 0 && tile == 0 && threadIdx.x == 0 && (2 * (kp1 + 2) + j * 16 + id) < a.trace_cap)
             marks[j * 16 + id] = wall_clock64();
     };
-    auto finish = [&](int k_done, int status, int nt) {
-        if (tile == 0 && threadIdx.x == 0) {
-            ctl->k_done = k_done;
-            ctl->nt = nt;
-            ctl->ng = 0;
-            if (ctl->status == 0) ctl->status = status;
-        }
+    // every right-hand side's status records a failed barrier
+    auto fail_all = [&](int status) {
+        if (tile == 0 && threadIdx.x == 0)
+            for (int b = 0; b < nrhs; ++b) rhs(b).ctl->status = status;
     };
-    auto fail = [&](int status) {
-        if (tile == 0 && threadIdx.x == 0) ctl->status = status;
-    };
-
-    if (!hbar_init(ctl, bs, (unsigned)G, a.timeout_ticks)) { fail(-3); return; }
+    if (!hbar_init(ctl, bs, (unsigned)G, a.timeout_ticks)) { fail_all(-3); return; }
 
     // ---- setup: v_0 = b (stored), argmax partial of b
-    {
+    for (int b = 0; b < nrhs; ++b) {
+        const RhsP R = rhs(b);
+        TB* V = (TB*)R.L;
+        const TO* bvec = (const TO*)R.b;
+        PivState pm{(int*)lds_at(a.lds_pl_m, b), (int*)lds_at(a.lds_pc_m, b), (unsigned*)lds_at(a.lds_bm_m, b),
+                    &s_cnt[b]};
         double acc[EPT];
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
@@ -174,7 +200,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             acc[i] = ((vm >> i) & 1u) ? (double)bv : 0.0;
             if ((vm >> i) & 1u) V[gm[i]] = (TB)bv;
         }
-        tile_argmax<EPT>(acc, gm, vm, a.amv + G, a.ami + G, tile);   // read as "previous" by step 0
+        tile_argmax<EPT>(acc, gm, vm, R.amv + G, R.ami + G, tile);   // read as "previous" by step 0
         if (a.psamp) {   // sample candidates of p_0 (values as stored)
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
                 const int yy = e / TX, xx = e - yy * TX;
@@ -183,72 +209,115 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             __syncthreads();
             sample_publish(a.spm, tile, wt, pm.bits, a.n, a.pnc, 0u, 0u, a.seed_lo, a.seed_hi,
-                           a.sval + SAMPLE_SLOTS, a.sidx + SAMPLE_SLOTS);
+                           R.sval + SAMPLE_SLOTS, R.sidx + SAMPLE_SLOTS);
         }
     }
-    if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+    if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail_all(-3); return; }
 
-    double scc = 1.0;
     for (int j = 0; j <= k; ++j) {
         const int par = j & 1;            // buffers written in this phase
         const int prv = par ^ 1;          // buffers written in the previous phase
-        // ---- 1. pivot p_j and eta_j = v_j(p_j) (wave 0), overlapped with
+        // ---- 1. pivot p_j and eta_j = v_j(p_j) of each right-hand side
+        //         (wave b for right-hand side b), overlapped with
         // ---- 2. the previous column's sketch rows of this workgroup's slice
-        //         (waves 1 .. NWAVE-1, one row per task)
-        double eta;
-        int p;
+        //         (the other waves, one row per task)
         // the first halo loads of v_j (stored before the barrier) go out
-        // here and overlap the pivot search
+        // here and overlap the pivot search (the first right-hand side)
         TB pre[BLUR_SB];
         unsigned pin = 0u;
-        blur_stage_issue<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, pre, pin);
+        blur_stage_issue<TB>((const TB*)a.L + (long long)j * a.ldl, ny, nx, r, a.bc, tm, TY, TX, pre, pin);
         mark(j, 0);
         {
             const int r0 = (int)(((long long)tile * a.s) / G), r1 = (int)(((long long)(tile + 1) * a.s) / G);
             const int nr = r1 - r0;
             const int ntask = (j >= 1 && a.stepsk) ? nr * ((j == 1 ? 1 : 0) + 1 + (a.lam > 0.0 ? 1 : 0)) : 0;
             const int wave = threadIdx.x >> 6;
-            if (wave == 0) {
-                global_argmax_wave(a.amv + prv * G, a.ami + prv * G, 0, G, &s_amv, &s_ami);
+            const int w0 = nrhs < NWAVE ? nrhs : NWAVE;     // waves taking an argmax
+            if (wave < nrhs && !s_done[wave]) {
+                const RhsP ab = rhs(wave);
+                global_argmax_wave(ab.amv + prv * G, ab.ami + prv * G, 0, G, &s_amv[wave], &s_ami[wave]);
                 if (a.psamp) {
                     double sv;
                     int si;
-                    const bool ok = sample_pivot_wave(a.sval + prv * SAMPLE_SLOTS, a.sidx + prv * SAMPLE_SLOTS,
+                    const bool ok = sample_pivot_wave(ab.sval + prv * SAMPLE_SLOTS, ab.sidx + prv * SAMPLE_SLOTS,
                                                       a.pnc, a.psamp, sv, si);
-                    if (ok && threadIdx.x == 0 && s_ami != -2) { s_amv = sv; s_ami = si; }
+                    if (ok && (threadIdx.x & 63) == 0 && s_ami[wave] != -2) { s_amv[wave] = sv; s_ami[wave] = si; }
                 }
-            } else {
-                for (int t = wave - 1; t < ntask; t += NWAVE - 1) {
-                    const int kind = t / nr, r = r0 + (t - kind * nr);
+            }
+            // sketch rows: on the waves left over, or on all waves after the
+            // argmax when every wave took one
+            if (w0 == NWAVE) __syncthreads();
+            const int tw0 = (w0 == NWAVE) ? 0 : w0, twn = NWAVE - tw0;
+            if (wave >= tw0) {
+                for (int t = wave - tw0; t < ntask * nrhs; t += twn) {
+                    const int b = t / max(ntask, 1), tt = t - b * ntask;
+                    if (s_done[b]) continue;
+                    const RhsP ab = rhs(b);
+                    const double* sc_b = (const double*)lds_at(a.lds_scale, b);
+                    const int kind = tt / nr, r = r0 + (tt - kind * nr);
                     // partials are FP64 for both sketch kinds in this kernel
                     if (kind == 0) {            // z_{j-1}
-                        reduce_row<SK_GAUSS>(a.zpart + prv * GS, G, a.s, r, inv_sk, a.Z + (long long)(j - 1) * a.s);
+                        reduce_row<SK_GAUSS>(ab.zpart + prv * GS, G, a.s, r, inv_sk, ab.Z + (long long)(j - 1) * a.s);
                     } else if (kind == 1 && a.lam > 0.0) {   // f_{j-1}
-                        reduce_row<SK_GAUSS>(a.fpart + prv * GS, G, a.s, r, inv_sk * sc_l[j - 1],
-                                             a.F + (long long)(j - 1) * a.s);
+                        reduce_row<SK_GAUSS>(ab.fpart + prv * GS, G, a.s, r, inv_sk * sc_b[j - 1],
+                                             ab.F + (long long)(j - 1) * a.s);
                     } else {                    // c = S2 b (after step 0)
-                        reduce_row<SK_GAUSS>(a.cpart, G, a.s, r, inv_sk, a.c);
+                        reduce_row<SK_GAUSS>(ab.cpart, G, a.s, r, inv_sk, ab.c);
                     }
                 }
             }
             __syncthreads();
-            // The argmax compares the values before rounding to the storage
-            // type; the pivot entry eta_j is the value as stored, so that
-            // l_j = s_j v_j has l_j(p_j) = 1 up to the FP64 reciprocal for
-            // every storage type.
-            eta = s_amv;
-            if constexpr (sizeof(TB) < sizeof(double)) eta = (double)(TB)eta;
-            p = s_ami;
         }
         mark(j, 1);
-        if (p == -2) { fail(-4); return; }
+      for (int b = 0; b < nrhs; ++b) {
+        if (s_done[b]) continue;          // uniform: written before a barrier
+        cur_b = b;
+        // this right-hand side's region: its pointers are recomputed where
+        // used (kernel argument + offset) rather than held in registers
+        const long long rst = (long long)b * a0.rhs_stride;
+        auto at = [&](auto* q) { return (decltype(q))((char*)q + rst); };
+        Ctl* ctl = at(a0.ctl);
+        TB* V = (TB*)a0.L + (long long)b * kp1 * a0.ldl;
+        const TO* bvec = (const TO*)a0.b + (long long)b * a0.m;
+        double* sc_l = (double*)lds_at(a0.lds_scale, b);     // s_j = 1 / eta_j
+        double* scf_l = sc_l + kp1;                           // fixed-point scale of f_j
+        TP* Pl = (TP*)lds_at(a0.lds_pD, b);
+        int* pivs = (int*)lds_at(a0.lds_pl_n, b);
+        int* wlist = (int*)lds_at(a0.lds_pc_n, b);
+        PivState pm{(int*)lds_at(a0.lds_pl_m, b), (int*)lds_at(a0.lds_pc_m, b), (unsigned*)lds_at(a0.lds_bm_m, b),
+                    &s_cnt[b]};
+        int& s_nwb = s_nw[b];
+        auto finish = [&](int k_done, int status, int nt) {
+            if (tile == 0 && threadIdx.x == 0) {
+                ctl->k_done = k_done;
+                ctl->nt = nt;
+                ctl->ng = 0;
+                if (ctl->status == 0) ctl->status = status;
+            }
+        };
+        auto done = [&]() {
+            if (threadIdx.x == 0) s_done[b] = 1;
+        };
+        // The argmax compares the values before rounding to the storage
+        // type; the pivot entry eta_j is the value as stored, so that
+        // l_j = s_j v_j has l_j(p_j) = 1 up to the FP64 reciprocal for
+        // every storage type.
+        double eta = s_amv[b];
+        if constexpr (sizeof(TB) < sizeof(double)) eta = (double)(TB)eta;
+        const int p = s_ami[b];
+        if (p == -2) {
+            if (tile == 0 && threadIdx.x == 0) ctl->status = -4;
+            done();
+            continue;
+        }
         const bool brk = (eta == 0.0) || (j >= a.n);
         mark(j, 2);
         if (brk) {
-            if (tile == 0 && threadIdx.x == 0 && j >= 1) a.H[(long long)(j - 1) * kp1 + j] = 0.0;
+            if (tile == 0 && threadIdx.x == 0 && j >= 1) at(a0.H)[(long long)(j - 1) * kp1 + j] = 0.0;
             if (j == 0) finish(0, 1, 0);
             else finish(j, (j < k) ? 1 : 0, j);
-            return;
+            done();
+            continue;
         }
         const double sj = 1.0 / eta;
         // |v_j| <= |eta_j|: fixed-point scale of the S1 v_j partial sums
@@ -256,15 +325,19 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         if (threadIdx.x == 0) {
             sc_l[j] = sj; scf_l[j] = scf_j; pivs[j] = p;
             const WBox bx = wbox(p, ny, nx, r, TY, TX);
-            if (tyi >= bx.tyl && tyi <= bx.tyh && txi >= bx.txl && txi <= bx.txh) wlist[s_nw++] = j;
+            if (tyi >= bx.tyl && tyi <= bx.tyh && txi >= bx.txl && txi <= bx.txh) wlist[s_nwb++] = j;
         }
         if (tile == 0 && threadIdx.x == 0) {
-            a.scale[j] = sj;
-            a.tp[j] = p;
-            if (j >= 1) a.H[(long long)(j - 1) * kp1 + j] = eta;
+            at(a0.scale)[j] = sj;
+            at(a0.tp)[j] = p;
+            if (j >= 1) at(a0.H)[(long long)(j - 1) * kp1 + j] = eta;
             else ctl->beta = eta;
         }
-        if (j == k) { finish(k, 0, k + 1); return; }
+        if (j == k) {
+            finish(k, 0, k + 1);
+            done();
+            continue;
+        }
         __syncthreads();
         // ---- 3. coefficients
         {
@@ -278,11 +351,11 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                 pm.bits[oe >> 5] |= 1u << (oe & 31);
             }
         }
-        if (j == 0) scc = fx_scale((double)a.m * fabs(eta) * 1.000001);
+        const double scc = fx_scale((double)a.m * fabs(eta) * 1.000001);   // used at j == 0
         mark(j, 3);
         double* pv = wred;                                   // pv[0..j]
         double* slotv = wred + kp1;                          // partials, [i * nslot + q]
-        const double* wpp = a.wpart + (long long)prv * kp1 * a.nslot;
+        const double* wpp = at(a0.wpart) + (long long)prv * kp1 * a.nslot;
         const TB* vj = V + (long long)j * ld;
         const int py = p / nx, px = p - py * nx;
         const int tot = j * a.nslot;
@@ -319,10 +392,8 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
             middle();
             // consume
-            if ((int)threadIdx.x < j) {
-                if (a.pinv) rrow[threadIdx.x] = sc_l[threadIdx.x] * (double)gv;
-                else Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TP)(sc_l[threadIdx.x] * (double)gv);
-            }
+            if ((int)threadIdx.x < j)
+                Pl[packed_col(threadIdx.x, k) + (j - threadIdx.x - 1)] = (TP)(sc_l[threadIdx.x] * (double)gv);
 #pragma unroll
             for (int u = 0; u < SBW; ++u) {
                 const int q = u * NT + (int)threadIdx.x;
@@ -360,73 +431,8 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int i = threadIdx.x; i <= j; i += 64) hs_l[i] = h_l[i] * sc_l[i];
             if (tile == 0)
-                for (int i = threadIdx.x; i <= j; i += 64) a.H[(long long)j * kp1 + i] = h_l[i];
+                for (int i = threadIdx.x; i <= j; i += 64) at(a0.H)[(long long)j * kp1 + i] = h_l[i];
             mark(j, 6);
-        };
-        // All waves: h = P_j^{-1} u(p) from M = P_{j-1}^{-1}, kept in LDS and
-        // extended by one row per step.  With r = P(j, 0:j-1) (rrow):
-        //   h_i = u_i + sum_{c<i} M(i, c) u_c           (i < j)
-        //   M(j, c) = -(r_c + sum_{c<i<j} r_i M(i, c))   (c < j)
-        //   h_j = u_j - sum_{c<j} r_c h_c
-        // Four lanes share each output (strided partial sums, then a quad
-        // reduction), so the chain is about j/4 FMAs instead of the j
-        // dependent steps of a substitution.  Ends with h_l, hs_l and column
-        // j of H written and the workgroup synchronised.
-        auto coef_solve_pinv = [&]() {
-            mark(j, 5);
-            const int q4 = threadIdx.x & 3;
-            constexpr int UB = 8;       // loads issued before their products
-            for (int t = (int)threadIdx.x >> 2; t < 2 * j; t += NT / 4) {
-                double sacc = 0.0;
-                if (t < j) {
-                    const double* mr = Ml + (t * (t - 1)) / 2;
-                    for (int c0 = q4; c0 < t; c0 += 4 * UB) {
-                        double mv[UB], uv[UB];
-#pragma unroll
-                        for (int u = 0; u < UB; ++u) {
-                            const int c = min(c0 + 4 * u, t - 1);
-                            mv[u] = mr[c];
-                            uv[u] = pv[c];
-                        }
-#pragma unroll
-                        for (int u = 0; u < UB; ++u)
-                            if (c0 + 4 * u < t) sacc = fma(mv[u], uv[u], sacc);
-                    }
-                } else {
-                    const int c = t - j;
-                    for (int i0 = c + 1 + q4; i0 < j; i0 += 4 * UB) {
-                        double rv[UB], mv[UB];
-#pragma unroll
-                        for (int u = 0; u < UB; ++u) {
-                            const int i = min(i0 + 4 * u, j - 1);
-                            rv[u] = rrow[i];
-                            mv[u] = Ml[(i * (i - 1)) / 2 + c];
-                        }
-#pragma unroll
-                        for (int u = 0; u < UB; ++u)
-                            if (i0 + 4 * u < j) sacc = fma(rv[u], mv[u], sacc);
-                    }
-                }
-                sacc += __shfl_xor(sacc, 1);
-                sacc += __shfl_xor(sacc, 2);
-                if (q4 == 0) {
-                    if (t < j) h_l[t] = pv[t] + sacc;
-                    else Ml[(j * (j - 1)) / 2 + (t - j)] = -(rrow[t - j] + sacc);
-                }
-            }
-            __syncthreads();
-            if (threadIdx.x < 64) {
-                double sacc = 0.0;
-                for (int c = threadIdx.x; c < j; c += 64) sacc = fma(rrow[c], h_l[c], sacc);
-                sacc = wave_sum(sacc);
-                if (threadIdx.x == 0) h_l[j] = pv[j] - sacc;
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i <= j; i += NT) hs_l[i] = h_l[i] * sc_l[i];
-            if (tile == 0)
-                for (int i = threadIdx.x; i <= j; i += NT) a.H[(long long)j * kp1 + i] = h_l[i];
-            mark(j, 6);
-            __syncthreads();
         };
         auto c_sketch = [&]() {   // c = S2 b: b itself when the basis type is narrower
             for (int e = threadIdx.x; e < TY * TX; e += NT) {
@@ -447,8 +453,13 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         const bool fsk = a.lam > 0.0 && a.stepsk;
         coef_loads([&]() {
             mark(j, 12);
-            blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert,
-                                 wt, pre, pin, (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
+            // the first right-hand side's halo loads went out before the
+            // argmax; the others issue theirs here
+            if (b == 0)
+                blur_tile_staged<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert,
+                                     wt, pre, pin, (marks && tile == 0) ? marks + j * 16 + 13 : nullptr);
+            else
+                blur_tile<TB>(V + (long long)j * ld, ny, nx, r, a.bc, tm, TY, TX, psf, stage, vert, wt);
             mark(j, 7);
         });
 #pragma unroll
@@ -463,18 +474,16 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
         }
         __syncthreads();
-        if (a.pinv) {
-            coef_solve_pinv();
-        } else if constexpr (SK == SK_SPARSE) {
+        if constexpr (SK == SK_SPARSE) {
             // wave 0 forms h while waves 1..7 form the sketch partials
             if (threadIdx.x < 64) {
                 coef_solve_wave();
             } else if (a.stepsk) {
                 // z_j partial = S2 u; f_j partial = S1 v_j (scaled by s_j when reduced)
-                sketch_rows_sum(wt, rows2, a.s, (double*)(a.zpart + par * GS + (long long)tile * a.s),
+                sketch_rows_sum(wt, rows2, a.s, (double*)(at(a0.zpart) + par * GS + (long long)tile * a.s),
                                 (int)threadIdx.x - 64, NT - 64);
                 if (fsk)
-                    sketch_rows_sum(vert, rows1, a.s, (double*)(a.fpart + par * GS + (long long)tile * a.s),
+                    sketch_rows_sum(vert, rows1, a.s, (double*)(at(a0.fpart) + par * GS + (long long)tile * a.s),
                                     (int)threadIdx.x - 64, NT - 64);
             }
         } else {
@@ -485,13 +494,13 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         if constexpr (SK == SK_SPARSE) {
             if (j == 0 && a.stepsk) {
                 c_sketch();
-                sketch_rows_partial(wt, rows2, a.s, (double*)(a.cpart + (long long)tile * a.s));
+                sketch_rows_partial(wt, rows2, a.s, (double*)(at(a0.cpart) + (long long)tile * a.s));
             }
         } else if (a.stepsk) {
-            sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, a.zpart + par * GS, tile);   // z_j
+            sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, a.scz, sk, at(a0.zpart) + par * GS, tile);   // z_j
             if (j == 0) {
                 c_sketch();
-                sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, a.cpart, tile);
+                sketch_partial<TO, SK>(a, wt, a.spm, tm, 2u, scc, sk, at(a0.cpart), tile);
             }
             if (a.lam > 0.0) {   // f_j partial = S1 v_j (scaled by s_j when reduced)
                 for (int e = threadIdx.x; e < TY * TX; e += NT) {
@@ -499,7 +508,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
                     wt[e] = (double)stage[(yy + r) * (TX + 2 * r) + xx + r];
                 }
                 __syncthreads();
-                sketch_partial<TO, SK>(a, wt, a.spm, tm, 1u, scf_j, sk, a.fpart + par * GS, tile);
+                sketch_partial<TO, SK>(a, wt, a.spm, tm, 1u, scf_j, sk, at(a0.fpart) + par * GS, tile);
             }
         }
         __syncthreads();
@@ -508,7 +517,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         eliminate_buf<TB, EPT>(acc, gm, V, ld, hs_l, j + 1);
         mark(j, 9);
         zero_pivots<EPT>(acc, vm, pm.bits);
-        tile_argmax<EPT>(acc, gm, vm, a.amv + par * G, a.ami + par * G, tile);
+        tile_argmax<EPT>(acc, gm, vm, at(a0.amv) + par * G, at(a0.ami) + par * G, tile);
         TB* dst = V + (long long)(j + 1) * ld;
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
@@ -520,7 +529,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         __syncthreads();
         if (a.psamp)   // sample candidates of p_{j+1} (values as stored)
             sample_publish(a.spm, tile, wt, pm.bits, a.n, a.pnc, (uint32_t)(j + 1), 0u, a.seed_lo, a.seed_hi,
-                           a.sval + par * SAMPLE_SLOTS, a.sidx + par * SAMPLE_SLOTS);
+                           at(a0.sval) + par * SAMPLE_SLOTS, at(a0.sidx) + par * SAMPLE_SLOTS);
         mark(j, 10);
         // window sums of A v_{j+1} at the pivots p_0..p_j over this tile's
         // pixels, one wave per pivot.  A window that stays inside the image
@@ -529,9 +538,9 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
         // and the separable weights are applied per column; a window folded
         // by the reflective boundary walks all its offsets.
         {
-            const int nw = s_nw;
+            const int nw = s_nwb;
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-            double* wpc = a.wpart + (long long)par * kp1 * a.nslot;
+            double* wpc = at(a0.wpart) + (long long)par * kp1 * a.nslot;
             for (int q = wave; q < nw; q += NWAVE) {
                 const int i = wlist[q];
                 const int p = pivs[i];
@@ -581,12 +590,22 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a)
             }
         }
         mark(j, 11);
+        if (b + 1 < nrhs) __syncthreads();   // the next right-hand side reuses the shared LDS buffers
+      }
+        cur_b = 0;
         // sampled arrival / release times of every workgroup (tracing only)
         unsigned long long* arr = (a.trace && (j & 7) == 4 && (j >> 3) < ARR_SAMPLES)
                                       ? a.trace + a.trace_cap + (long long)(j >> 3) * 2 * MAXG : nullptr;
         if (arr && threadIdx.x == 0) arr[tile] = wall_clock64();
-        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail(-3); return; }
+        if (!hbar_sync(ctl, bs, a.timeout_ticks, a.trace, a.trace_cap)) { fail_all(-3); return; }
         if (arr && threadIdx.x == 0) arr[MAXG + tile] = wall_clock64();
+        // every right-hand side has finished (the flags were set before the
+        // barrier, in every workgroup alike)
+        {
+            bool all = true;
+            for (int b = 0; b < nrhs; ++b) all = all && s_done[b];
+            if (all) return;
+        }
     }
 }
 

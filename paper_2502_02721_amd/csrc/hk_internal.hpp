@@ -13,6 +13,7 @@ constexpr int KSLOT = 4;            // (KMAX+1)/64
 constexpr int MAX_EPT = 4;          // elements per thread of a tile (tile <= 2048 elements)
 constexpr int MAXG = 256;           // workgroups of the persistent kernel (one per CU)
 constexpr int SAMPLE_MAX = 64;      // largest pivot sample
+constexpr int RMAX = 8;             // right-hand sides a solve advances together
 constexpr int SAMPLE_SLOTS = 4 * ((SAMPLE_MAX + 3) / 4 + 2);   // candidate slots per search
 // a whole basis (at most NT * MAX_EPT * MAXG elements per column, KMAX + 1
 // FP64 columns) is addressed by 32-bit byte offsets of one buffer resource
@@ -127,9 +128,13 @@ struct KArgs {
     int nslot, spx;             // slots per pivot, slots per row of the window box
     int lds_scale, lds_hs, lds_wred;
     int lds_skt;                // sparse-sign tables (0: built on the fly)
-    // coefficients from M = P^{-1} (FP64, rows packed, extended by one row per
-    // step) instead of a forward substitution on P; row j of P in FP64
-    int pinv, lds_rrow;
+    // right-hand sides advanced together (single-barrier blur kernel): each
+    // has a workspace region rhs_stride bytes after the previous one (its
+    // basis: (k + 1) columns after the previous one's in L; its b: m
+    // elements further on) and an LDS block lds_rhs bytes further on
+    int nrhs;
+    long long rhs_stride;
+    int lds_rhs;
     // CSR operators: the row pointers of the workgroup's m-tile and n-tile
     // rows, relative to the tile's first entry (int32), staged once per solve
     // (-1: not staged, read from global memory)
@@ -156,7 +161,27 @@ struct LsArgs {
     double* Q; double* R; double* r; double* y; double* res; double* d;
     Ctl* ctl;
     unsigned long long* trace;   // LS_TRACE timestamps, or null
+    // several right-hand sides: workgroup b solves the problem whose Z, F,
+    // Q, R, r, y, res, d and ctl lie b * rhs_stride bytes further on, with
+    // c b * c_stride doubles further on
+    int nrhs;
+    long long rhs_stride;
+    long long c_stride;
 };
+
+// The small problem of right-hand side b (the workgroup's).
+__device__ __forceinline__ LsArgs ls_rebase(const LsArgs& a0, int b)
+{
+    LsArgs a = a0;
+    if (b == 0) return a;
+    const long long st = (long long)b * a0.rhs_stride;
+    auto sh = [&](auto* q) { return q ? (decltype(q))((const char*)q + st) : q; };
+    a.Z = sh(a0.Z); a.F = sh(a0.F); a.Q = sh(a0.Q); a.R = sh(a0.R); a.r = sh(a0.r);
+    a.y = sh(a0.y); a.res = sh(a0.res); a.d = sh(a0.d); a.ctl = sh(a0.ctl);
+    a.c = a0.c + (long long)b * a0.c_stride;
+    a.trace = nullptr;
+    return a;
+}
 constexpr int LS_TRACE = 256;    // timestamp slots of the least-squares kernel
 // per-workgroup barrier arrival / release timestamps of the blur kernel at
 // steps j = 8 q + 4 (q < ARR_SAMPLES): ARR_SAMPLES x 2 x MAXG slots after the
@@ -171,6 +196,9 @@ struct CombineArgs {
     const double* scale;         // per-column scale of the stored basis, or null
     void* x;
     const Ctl* ctl;
+    // right-hand side blockIdx.y: its basis (k + 1) columns further on, x n
+    // elements further on, y, scale and ctl rhs_stride bytes further on
+    long long rhs_stride;
 };
 
 struct ApplyArgs {
@@ -192,7 +220,7 @@ hipError_t launch_ctl_init(Ctl* ctl, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);   // p, bytes: multiples of 16
 hipError_t launch_solve_info(const Ctl* ctl, int32_t* info, hipStream_t st);
 hipError_t launch_small_ls(const LsArgs& a, hipStream_t st);
-hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st);
+hipError_t launch_combine(int tb, int to, const CombineArgs& a, int nrhs, hipStream_t st);
 // block sketch C = S B with S generated (hk_bsk.hip)
 struct BskArgs {
     const void* q;              // B: len x ncol, column-major, leading dimension ldq

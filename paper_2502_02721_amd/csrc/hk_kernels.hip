@@ -28,8 +28,9 @@ __device__ double block_sum_ls(double v, double* red)
     return t;
 }
 
-__global__ __launch_bounds__(LS_NT) void small_ls_kernel(LsArgs a)
+__global__ __launch_bounds__(LS_NT) void small_ls_kernel(LsArgs a_in)
 {
+    const LsArgs a = ls_rebase(a_in, blockIdx.x);     // one workgroup per right-hand side
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[LS_NW];
     for (int i = threadIdx.x; i < a.k; i += LS_NT) a.res[i] = 0.0;
@@ -118,15 +119,20 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
-    const TB* L = (const TB*)a.L;
-    TO* x = (TO*)a.x;
-    const int st = a.ctl->status;
-    const int kd = (st < 0) ? 0 : a.ctl->k_done;
+    const int b = blockIdx.y;                           // right-hand side
+    const long long st_b = (long long)b * a.rhs_stride;
+    const TB* L = (const TB*)a.L + (long long)b * (a.k + 1) * a.ldl;
+    TO* x = (TO*)a.x + (long long)b * a.n;
+    const Ctl* ctl = (const Ctl*)((const char*)a.ctl + st_b);
+    const double* y = (const double*)((const char*)a.y + st_b);
+    const double* scale = a.scale ? (const double*)((const char*)a.scale + st_b) : nullptr;
+    const int st = ctl->status;
+    const int kd = (st < 0) ? 0 : ctl->k_done;
     double acc = 0.0;
-    if (a.scale) {
-        for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], a.y[j] * a.scale[j], acc);
+    if (scale) {
+        for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], y[j] * scale[j], acc);
     } else {
-        for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], a.y[j], acc);
+        for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], y[j], acc);
     }
     x[i] = (TO)acc;
 }
@@ -301,13 +307,13 @@ hipError_t launch_small_ls(const LsArgs& a, hipStream_t st)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(small_ls_kernel, dim3(1), dim3(LS_NT), lds, st, a);
+    hipLaunchKernelGGL(small_ls_kernel, dim3(std::max(1, a.nrhs)), dim3(LS_NT), lds, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int tb, int to, const CombineArgs& a, hipStream_t st)
+hipError_t launch_combine(int tb, int to, const CombineArgs& a, int nrhs, hipStream_t st)
 {
-    const int blocks = (a.n + 255) / 256;
+    const dim3 blocks((a.n + 255) / 256, std::max(1, nrhs));
     if (tb == 0 && to == 0) hipLaunchKernelGGL((combine_kernel<double, double>), dim3(blocks), dim3(256), 0, st, a);
     else if (tb == 1 && to == 1) hipLaunchKernelGGL((combine_kernel<float, float>), dim3(blocks), dim3(256), 0, st, a);
     else if (tb == 0 && to == 1) hipLaunchKernelGGL((combine_kernel<double, float>), dim3(blocks), dim3(256), 0, st, a);

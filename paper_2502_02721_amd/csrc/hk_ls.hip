@@ -17,6 +17,8 @@
 // and y = R^{-1} d.
 #include "hk_device.hpp"
 
+#include <algorithm>
+
 namespace hk {
 
 constexpr int LSB_NT = 512;
@@ -380,8 +382,9 @@ __device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, do
 }
 
 template <int NB>
-__global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a)
+__global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
 {
+    const LsArgs a = ls_rebase(a_in, blockIdx.x);     // one workgroup per right-hand side
     static_assert(NB == PNB, "panel width is the MFMA tile");
     extern __shared__ __align__(16) unsigned char smem[];
     // timestamps: slot 0 start, 1 end, 8 + 8 b + id for panel b
@@ -647,7 +650,7 @@ hipError_t launch_small_ls_blocked(int nb, const LsArgs& a, hipStream_t st)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(small_ls_blocked_kernel<PNB>, dim3(1), dim3(LSB_NT), lds, st, a);
+    hipLaunchKernelGGL(small_ls_blocked_kernel<PNB>, dim3(std::max(1, a.nrhs)), dim3(LSB_NT), lds, st, a);
     return hipGetLastError();
 }
 

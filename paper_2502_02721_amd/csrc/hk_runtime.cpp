@@ -131,6 +131,10 @@ struct hk_solve {
     // T = S2 [basis of the data space], c = S2 b, T1 = S1 L_k, then Z, F
     bool zend = false;
     BskArgs bz{}, bc{}, bf{};
+    int nrhs = 1;                          // right-hand sides advanced together
+    int sel = 0;                           // the one the getters report
+    double* call = nullptr;                // S2 b of the first right-hand side (the others follow)
+    size_t region = 0;                     // bytes between right-hand sides' regions
     double* T = nullptr;
     double* T1 = nullptr;
     long long runs = 0;                    // runs launched
@@ -140,6 +144,9 @@ struct hk_solve {
     hk_status last = HK_OK;
     int k_done = 0;
     int nt = 0, ng = 0;
+    // per right-hand side, after a wait: status, basis columns, pivots found
+    int rst[RMAX] = {}, rkd[RMAX] = {}, rnt[RMAX] = {}, rng[RMAX] = {};
+    bool aborted = false;                  // the last run's grid barrier timed out
 };
 
 namespace {
@@ -221,10 +228,10 @@ int spx_of(int r, int TX) { return (2 * r + 1 + TX - 1) / TX + 1; }
 int nslot_of(int r, int TY, int TX) { return spx_of(r, TX) * ((2 * r + 1 + TY - 1) / TY + 1); }
 
 // LDS of the single-barrier blur kernel; 0 if it does not fit.  zeta > 0:
-// the per-step sparse-sign row lists; pinv: M = P^{-1} in FP64 (else P in
-// the pivot-block type).
+// the per-step sparse-sign row lists; nrhs: right-hand sides, each with its
+// own block of what it keeps across steps.
 int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, int ntap, int tb, int zeta,
-                      int pinv, size_t lds_max)
+                      int nrhs, size_t lds_max)
 {
     a.lds_rp_m = a.lds_rp_n = -1;
     size_t off = 0;
@@ -236,14 +243,7 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
     const int kp1 = k + 1;
     a.lds_h = take(sizeof(double) * (KMAX + 1));
     a.lds_hs = take(sizeof(double) * (KMAX + 1));
-    a.lds_scale = take(sizeof(double) * 2 * (KMAX + 1));
     a.lds_w = take(sizeof(double) * NT * ept);
-    a.lds_pl_m = take(sizeof(int) * kp1);
-    a.lds_pc_m = take(sizeof(int) * kp1);
-    a.lds_bm_m = take(sizeof(unsigned) * ((NT * ept + 31) / 32));
-    a.lds_pl_n = take(sizeof(int) * kp1);      // all pivots
-    a.lds_pc_n = take(sizeof(int) * kp1);      // window list
-    a.lds_bm_n = a.lds_bm_m;
     const size_t ng = (size_t)(s + 3) / 4;
     a.lds_sk = take(sizeof(double) * std::max<size_t>((size_t)s, 4 * ng));
     const int SW = TX + 2 * r, SH = TY + 2 * r;
@@ -251,10 +251,6 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
     a.lds_vert = take(sizeof(double) * (size_t)TY * SW);
     a.lds_taps = take(psf_lds_bytes(r, ntap));
     a.lds_wred = take(sizeof(double) * (size_t)kp1 * (size_t)std::max(NWAVE, 1 + nslot_of(r, TY, TX)));
-    a.pinv = pinv;
-    a.lds_pD = take((pinv ? sizeof(double) : pdsize(tb)) * (size_t)packed_size(k));
-    a.lds_pL = a.lds_pD;
-    a.lds_rrow = pinv ? take(sizeof(double) * (size_t)kp1) : 0;
     a.pmode = 0;
     a.lds_skt = 0;
     if (zeta > 0) {
@@ -263,18 +259,28 @@ int lds_layout_onebar(KArgs& a, int k, int s, int ept, int TY, int TX, int r, in
         const size_t tabs = sizeof(unsigned) * 2 * (size_t)(s + 1) + sizeof(unsigned short) * 2 * (size_t)TY * TX * (size_t)zeta;
         a.lds_skt = take(tabs);
     }
+    // what each right-hand side keeps across steps, one block per right-hand
+    // side: the scales s_j and f_j scales, this tile's pivots, all pivots,
+    // the window list and the pivot block P
+    const size_t rb = off;
+    a.lds_scale = take(sizeof(double) * 2 * (size_t)kp1);
+    a.lds_pl_m = take(sizeof(int) * kp1);
+    a.lds_pc_m = take(sizeof(int) * kp1);
+    a.lds_bm_m = take(sizeof(unsigned) * ((NT * ept + 31) / 32));
+    a.lds_pl_n = take(sizeof(int) * kp1);      // all pivots
+    a.lds_pc_n = take(sizeof(int) * kp1);      // window list
+    a.lds_bm_n = a.lds_bm_m;
+    a.lds_pD = take(pdsize(tb) * (size_t)packed_size(k));
+    a.lds_pL = a.lds_pD;
+    a.lds_rhs = (int)(off - rb);
+    off = rb + (size_t)std::max(1, nrhs) * (size_t)a.lds_rhs;
     if (off > lds_max) return 0;
     a.lds_total = (int)off;
     return a.lds_total;
 }
 
-// Sketch partials every step: sparse sign, and Gaussian with 16-bit bases
-// (FP64 and FP32 bases take the Gaussian sketch at the end of the solve).
-bool per_step_sketch(const hk_params* p)
-{
-    if (p->sketch == HK_SKETCH_SPARSE_SIGN) return true;
-    return p->sketch == HK_SKETCH_GAUSSIAN && (p->basis_dtype == HK_BF16 || p->basis_dtype == HK_F16);
-}
+// Right-hand sides a solve advances together (0 in the parameters means 1).
+int nrhs_of(const hk_params* p) { return p->nrhs > 1 ? p->nrhs : 1; }
 
 Space range_space(int64_t len, int G)
 {
@@ -328,20 +334,18 @@ Plan plan_solve(const hk_op* op, const hk_params* p, int rect, int max_blocks, s
             pl.ept = (TY * TX + NT - 1) / NT;
             if (pl.ept > 2) pl.ept = 4;
             const int tabs = p->sketch == HK_SKETCH_SPARSE_SIGN ? p->zeta : 0;   // sparse-sign row lists
-            // Coefficients from M = P^{-1} (all waves, about j/4 dependent
-            // products) where no per-step sketch runs beside the
-            // substitution on wave 0, and for FP32 bases only: for FP64
-            // bases the substitution keeps the elimination's own order of
-            // operations, the closest to the sequential elimination.
-            const int pinv = (tb == HK_F32 && !per_step_sketch(p)) ? 1 : 0;
-            if ((pinv && lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, op->ntap, tb, tabs, 1, lds_max)) ||
-                lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, op->ntap, tb, tabs, 0, lds_max)) {
+            if (lds_layout_onebar(pl.lds, p->k, p->s, pl.ept, TY, TX, op->r, op->ntap, tb, tabs, nrhs_of(p),
+                                  lds_max)) {
                 pl.kernel = OP_BLUR_ONEBAR;
                 pl.lds_total = pl.lds.lds_total;
                 pl.spx = spx_of(op->r, TX);
                 pl.nslot = nslot_of(op->r, TY, TX);
             } else if (tb == HK_BF16 || tb == HK_F16) {
                 pl.why = "16-bit bases need the single-barrier blur kernel, whose LDS plan does not fit";
+                return pl;
+            } else if (nrhs_of(p) > 1) {
+                pl.why = "the right-hand sides' state does not fit the single-barrier kernel's LDS "
+                         "(fewer right-hand sides or a smaller k)";
                 return pl;
             } else {
                 pl.kernel = OP_BLUR;
@@ -391,6 +395,15 @@ hk_status validate(const hk_op* op, const hk_params* p, int* rect)
     if (p->max_workgroups < 0) return fail(HK_EINVAL, "max_workgroups must be >= 0");
     if (p->pivot_sample < 0 || p->pivot_sample > SAMPLE_MAX)
         return fail(HK_EINVAL, "pivot_sample = %d must be in [0, %d]", p->pivot_sample, SAMPLE_MAX);
+    if (p->nrhs < 0 || p->nrhs > RMAX) return fail(HK_EINVAL, "nrhs = %d must be in [0, %d]", p->nrhs, RMAX);
+    if (p->nrhs > 1) {
+        if (op->kind != OP_BLUR)
+            return fail(HK_EUNSUPPORTED, "several right-hand sides are implemented for blur operators");
+        if (p->pivot_sample > 0)
+            return fail(HK_EUNSUPPORTED, "several right-hand sides take full partial pivoting");
+        if (p->basis_dtype != HK_F64 && p->basis_dtype != HK_F32)
+            return fail(HK_EUNSUPPORTED, "several right-hand sides need FP64 or FP32 bases");
+    }
     if (p->sketch != HK_SKETCH_NONE && p->s > 16384)
         return fail(HK_EUNSUPPORTED, "sketch size s = %d exceeds 16384", p->s);
     if (p->basis_dtype < HK_F64 || p->basis_dtype > HK_F16)
@@ -419,8 +432,11 @@ int grid_cap(const hk_context* ctx, const hk_params* p)
 }
 
 // Block sketch of `ncol` columns of length `len` by s rows: 64 x 64 output
-// tiles times chunks of the contraction, about 1024 workgroups in all.
-BskArgs bsk_plan(int64_t len, int ncol, int s)
+// tiles times chunks of the contraction, about 1024 workgroups in all for
+// `ncol_ref` columns (0: ncol).  The chunks fix the order in which each
+// entry's sum is formed, so several right-hand sides' columns (ncol_ref =
+// one right-hand side's) are summed exactly as a single one's.
+BskArgs bsk_plan(int64_t len, int ncol, int s, int ncol_ref = 0)
 {
     BskArgs b{};
     b.len = (int)len;
@@ -428,7 +444,8 @@ BskArgs bsk_plan(int64_t len, int ncol, int s)
     b.s = s;
     b.rt = (s + 63) / 64;
     b.ct = (ncol + 63) / 64;
-    const int64_t kc0 = std::max<int64_t>(1, (1024 + b.rt * b.ct - 1) / (b.rt * b.ct));
+    const int ct_ref = ((ncol_ref > 0 ? ncol_ref : ncol) + 63) / 64;
+    const int64_t kc0 = std::max<int64_t>(1, (1024 + b.rt * ct_ref - 1) / (b.rt * ct_ref));
     const int64_t per = (len + kc0 - 1) / kc0;
     b.chunk = (int)std::max<int64_t>(16, (per + 15) / 16 * 16);
     b.kc = (int)((len + b.chunk - 1) / b.chunk);
@@ -437,9 +454,9 @@ BskArgs bsk_plan(int64_t len, int ncol, int s)
     return b;
 }
 
-size_t bsk_tiles(int64_t len, int ncol, int s)
+size_t bsk_tiles(int64_t len, int ncol, int s, int ncol_ref = 0)
 {
-    const BskArgs b = bsk_plan(len, ncol, s);
+    const BskArgs b = bsk_plan(len, ncol, s, ncol_ref);
     return (size_t)b.rt * b.ct * b.kc;
 }
 
@@ -457,7 +474,8 @@ hk_params effective_params(const hk_params& p)
 
 struct WsLayout {
     size_t ctl, L, D, H, W, tp, gp, PD, PL, pvD, pvL, amv, ami, zpart, fpart, cpart, Z, F, c;
-    size_t Q, R, r, y, res, d, trace, scale, wpart, sval, sidx, T, T1, part, total;
+    size_t Q, R, r, y, res, d, trace, scale, wpart, sval, sidx, T, T1, call, part, total;
+    size_t region;          // bytes of one right-hand side's region (regions first, side by side)
     int trace_cap;
     int64_t ldl, ldd;
 };
@@ -504,17 +522,25 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
     w.scale = take(sizeof(double) * kp1);
     w.wpart = take(sizeof(double) * 2 * (size_t)kp1 * std::max(1, nslot));
     w.sval = take(sizeof(double) * 4 * SAMPLE_SLOTS);
+    w.sidx = take(sizeof(int) * 4 * SAMPLE_SLOTS);
+    // one region per right-hand side, then what they share: the
+    // end-of-solve block sketches of all their bases and b's, and the bases
+    const int nr = nrhs_of(p);
+    w.region = off;
+    off = w.region * (size_t)nr;
     if (p->sketch == HK_SKETCH_GAUSSIAN && (p->basis_dtype == HK_F64 || p->basis_dtype == HK_F32)) {   // end-of-solve block sketches
-        w.T = take(sizeof(double) * (size_t)s * kp1);
-        w.T1 = take(sizeof(double) * (size_t)s * k);
+        const int nc = nr * kp1;
+        w.T = take(sizeof(double) * (size_t)s * nc);
+        w.T1 = take(sizeof(double) * (size_t)s * nc);
+        w.call = take(sizeof(double) * (size_t)s * nr);
         const int64_t lz = rect ? op->m : op->n;
-        const size_t tiles = std::max(std::max(bsk_tiles(lz, kp1, s), bsk_tiles(op->m, 1, s)), bsk_tiles(op->n, k, s));
+        const size_t tiles = std::max(std::max(bsk_tiles(lz, nc, s, kp1), bsk_tiles(op->m, nr, s, 1)),
+                                      bsk_tiles(op->n, nc, s, kp1));
         w.part = take(sizeof(double) * 4096 * tiles);
     }
-    w.sidx = take(sizeof(int) * 4 * SAMPLE_SLOTS);
     // the bases last: every column a run reads it has written first, so a
     // reused workspace needs only [0, L) cleared
-    w.L = take(es * (size_t)w.ldl * kp1);
+    w.L = take(es * (size_t)w.ldl * kp1 * nr);
     w.D = rect ? take(es * (size_t)w.ldd * kp1) : 0;
     w.total = off;
     return w;
@@ -964,26 +990,39 @@ static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rec
     a.spx = pl.spx;
     a.trace_cap = w.trace_cap;
     a.trace = w.trace_cap ? (unsigned long long*)(base + w.trace) : nullptr;
+    const int nr = nrhs_of(p);
+    sv->nrhs = nr;
+    a.nrhs = nr;
+    a.rhs_stride = (long long)w.region;
+    a.lds_rhs = pl.lds.lds_rhs;
+    sv->region = w.region;
+    sv->call = a.c;
     if (sv->zend) {
+        // one block contraction per sketch over every right-hand side's
+        // basis (side by side in L) or b: S is generated once per 64
+        // columns of the block, whatever the number of right-hand sides
         const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
+        const int nc = nr * (p->k + 1);
         sv->T = (double*)(base + w.T);
         sv->T1 = (double*)(base + w.T1);
+        sv->call = (double*)(base + w.call);
         double* part = (double*)(base + w.part);
-        // T = S2 [d_1 .. d_{k+1}] (the data-space basis)
-        sv->bz = bsk_plan(rect ? op->m : op->n, p->k + 1, p->s);
+        // T = S2 [d_1 .. d_{k+1}] (the data-space basis) of each right-hand side
+        sv->bz = bsk_plan(rect ? op->m : op->n, nc, p->s, p->k + 1);
         sv->bz.q = rect ? a.D : a.L;
         sv->bz.ldq = rect ? a.ldd : a.ldl;
         sv->bz.stream = 2u; sv->bz.k0 = k0; sv->bz.k1 = k1;
         sv->bz.part = part;
         sv->bz.out = sv->T;
-        // c = S2 b (b is set per run)
-        sv->bc = bsk_plan(op->m, 1, p->s);
+        // c = S2 b of each right-hand side (b is set per run)
+        sv->bc = bsk_plan(op->m, nr, p->s, 1);
         sv->bc.ldq = op->m;
         sv->bc.stream = 2u; sv->bc.k0 = k0; sv->bc.k1 = k1;
         sv->bc.part = part;
-        sv->bc.out = a.c;
-        // T1 = S1 [l_1 .. l_k]
-        sv->bf = bsk_plan(op->n, p->k, p->s);
+        sv->bc.out = sv->call;
+        // T1 = S1 [l_1 .. l_{k+1}] of each right-hand side (its first k
+        // columns are F)
+        sv->bf = bsk_plan(op->n, nc, p->s, p->k + 1);
         sv->bf.q = a.L;
         sv->bf.ldq = a.ldl;
         sv->bf.stream = 1u; sv->bf.k0 = k0; sv->bf.k1 = k1;
@@ -1003,8 +1042,13 @@ static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rec
     l.d = (double*)(base + w.d);
     l.ctl = a.ctl;
     l.trace = w.trace_cap ? a.trace + w.trace_cap + ARR_SLOTS : nullptr;
+    l.nrhs = nr;
+    l.rhs_stride = (long long)w.region;
+    l.c = sv->call;                               // S2 b of right-hand side b: c_stride doubles further on
+    l.c_stride = sv->zend ? p->s : (long long)(w.region / sizeof(double));
     CombineArgs& c = sv->ca;
     c.n = (int)op->n; c.k = p->k; c.L = a.L; c.ldl = a.ldl; c.y = l.y; c.ctl = a.ctl;
+    c.rhs_stride = (long long)w.region;
     c.scale = (pl.kernel == OP_BLUR_ONEBAR) ? a.scale : nullptr;
     l.nb = small_ls_panel(p->s, p->k, p->lambda, op->ctx->lds_max);
     if (l.nb == 0 && (size_t)small_ls_lds_bytes(p->s, p->k, p->lambda) > op->ctx->lds_max)
@@ -1069,11 +1113,16 @@ static hk_status solve_enqueue(hk_solve* sv, const void* b_dev, void* x_dev, hip
 {
     KArgs a = sv->ka;
     a.b = b_dev;
-    HIP_TRY(launch_ctl_init(a.ctl, s));
+    const int nr = sv->nrhs;
+    // right-hand side b's region: the same layout, b * region bytes further on
+    auto at = [&](auto* q, int b) { return (decltype(q))((char*)q + (size_t)b * sv->region); };
+    for (int b = 0; b < nr; ++b) HIP_TRY(launch_ctl_init(at(a.ctl, b), s));
     if (e0) HIP_TRY(hipEventRecord(e0, s));
     HIP_TRY(launch_iterate(sv->tb, sv->op->dtype, sv->kernel, sv->sk, sv->ept, a, s));
     if (e1) HIP_TRY(hipEventRecord(e1, s));
-    if (a.nosk) HIP_TRY(launch_hess_rhs(a.F, a.c, sv->prm.s, sv->prm.k, sv->prm.lambda, a.ctl, s));
+    if (a.nosk)
+        for (int b = 0; b < nr; ++b)
+            HIP_TRY(launch_hess_rhs(at(a.F, b), at(a.c, b), sv->prm.s, sv->prm.k, sv->prm.lambda, at(a.ctl, b), s));
     if (sv->zend) {
         // Gaussian sketches of the whole basis: Z = (S2 D_{k+1}) H_{k+1,k},
         // F = S1 L_k, c = S2 b (the Gaussian entries in the data's precision)
@@ -1084,14 +1133,16 @@ static hk_status solve_enqueue(hk_solve* sv, const void* b_dev, void* x_dev, hip
         bc.q = b_dev;
         HIP_TRY(launch_block_sketch(sv->op->dtype == HK_F64 ? 0 : 1, tg, bc, s));
         if (fz) HIP_TRY(launch_block_sketch(sv->tb, tg, sv->bf, s));
-        HIP_TRY(launch_sketch_finish(sv->T, fz ? sv->T1 : nullptr, a.H,
-                                     sv->kernel == OP_BLUR_ONEBAR ? a.scale : nullptr, sv->prm.s, sv->prm.k, a.Z,
-                                     a.F, s));
+        const long long cs = (long long)sv->prm.s * (sv->prm.k + 1);   // one right-hand side's columns of T
+        for (int b = 0; b < nr; ++b)
+            HIP_TRY(launch_sketch_finish(sv->T + b * cs, fz ? sv->T1 + b * cs : nullptr, at(a.H, b),
+                                         sv->kernel == OP_BLUR_ONEBAR ? at(a.scale, b) : nullptr, sv->prm.s,
+                                         sv->prm.k, at(a.Z, b), at(a.F, b), s));
     }
     HIP_TRY(launch_small_ls(sv->la, s));
     CombineArgs c = sv->ca;
     c.x = x_dev;
-    HIP_TRY(launch_combine(sv->tb, sv->op->dtype, c, s));
+    HIP_TRY(launch_combine(sv->tb, sv->op->dtype, c, nr, s));
     if (e2) HIP_TRY(hipEventRecord(e2, s));
     return HK_OK;
 }
@@ -1166,23 +1217,60 @@ hk_status hk_solve_wait(hk_solve* sv)
     hk_status st = current_device(sv->op->ctx);
     if (st) return st;
     HIP_TRY(hipEventSynchronize(sv->ev2));
-    Ctl ctl;
-    HIP_TRY(hipMemcpy(&ctl, sv->ka.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    // every right-hand side's control block (the first also holds the
+    // barrier's abort flag); the run's status is the worst of them
+    bool abort = false;
+    int worst = HK_OK, bad = -1;
+    for (int b = 0; b < sv->nrhs; ++b) {
+        Ctl ctl;
+        HIP_TRY(hipMemcpy(&ctl, (const char*)sv->ka.ctl + (size_t)b * sv->region, sizeof(Ctl), hipMemcpyDeviceToHost));
+        if (b == 0) abort = ctl.abort != 0;
+        sv->rst[b] = ctl.status;
+        sv->rkd[b] = ctl.k_done;
+        sv->rnt[b] = ctl.nt;
+        sv->rng[b] = ctl.ng;
+        if (ctl.status < 0 && bad < 0) bad = b;
+        if (ctl.status == HK_BREAKDOWN && worst == HK_OK) worst = HK_BREAKDOWN;
+    }
     sv->waited = true;
-    sv->k_done = ctl.k_done;
-    sv->nt = ctl.nt;
-    sv->ng = ctl.ng;
-    if (ctl.abort) sv->last = fail(HK_EDEVICE, "grid barrier timed out: the basis kernel was aborted");
-    else if (ctl.status < 0) sv->last = fail(ctl.status, ctl.status == HK_ENUMERIC ? "non-finite values or a rank-deficient sketched problem" : "device error %d", ctl.status);
-    else sv->last = ctl.status;
+    sv->aborted = abort;
+    sv->k_done = sv->rkd[sv->sel];
+    sv->nt = sv->rnt[sv->sel];
+    sv->ng = sv->rng[sv->sel];
+    if (abort) {
+        sv->last = fail(HK_EDEVICE, "grid barrier timed out: the basis kernel was aborted");
+    } else if (bad >= 0) {
+        const int st = sv->rst[bad];
+        sv->last = fail(st, st == HK_ENUMERIC ? "right-hand side %d: non-finite values or a rank-deficient sketched problem"
+                                              : "right-hand side %d: device error %d", bad, st);
+    } else {
+        sv->last = worst;
+    }
     return sv->last;
 }
 
+hk_status hk_solve_select_rhs(hk_solve* sv, int32_t rhs)
+{
+    if (!sv) return fail(HK_EINVAL, "null solve");
+    if (rhs < 0 || rhs >= sv->nrhs) return fail(HK_EINVAL, "right-hand side %d outside [0, %d)", rhs, sv->nrhs);
+    sv->sel = rhs;
+    sv->k_done = sv->rkd[rhs];
+    sv->nt = sv->rnt[rhs];
+    sv->ng = sv->rng[rhs];
+    return HK_OK;
+}
+
+// The last run has finished and the selected right-hand side's results are
+// valid: an error of another right-hand side does not hide them.
 static hk_status ensure_done(hk_solve* sv)
 {
     if (!sv) return fail(HK_EINVAL, "null solve");
     hk_status st = hk_solve_wait(sv);
-    return st < 0 ? st : HK_OK;
+    if (st >= 0) return HK_OK;
+    if (sv->nrhs > 1 && !sv->aborted && sv->rst[sv->sel] >= 0) return HK_OK;
+    if (sv->nrhs > 1 && !sv->aborted)
+        return fail(sv->rst[sv->sel], "right-hand side %d: status %d", sv->sel, sv->rst[sv->sel]);
+    return st;
 }
 
 hk_status hk_solve_info(hk_solve* sv, int32_t* k_done)
@@ -1190,7 +1278,7 @@ hk_status hk_solve_info(hk_solve* sv, int32_t* k_done)
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (k_done) *k_done = sv->k_done;
-    return sv->last;
+    return sv->nrhs > 1 ? sv->rst[sv->sel] : sv->last;
 }
 
 hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W)
@@ -1198,7 +1286,8 @@ hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W)
     hk_status st = ensure_done(sv);
     if (st) return st;
     const int k = sv->prm.k;
-    if (H) HIP_TRY(hipMemcpy(H, sv->ka.H, sizeof(double) * (size_t)(k + 1) * k, hipMemcpyDeviceToHost));
+    const size_t ro = (size_t)sv->sel * sv->region;     // the selected right-hand side's region
+    if (H) HIP_TRY(hipMemcpy(H, (const char*)sv->ka.H + ro, sizeof(double) * (size_t)(k + 1) * k, hipMemcpyDeviceToHost));
     if (W) {
         if (!sv->rect) return fail(HK_EINVAL, "W exists for the generalized Hessenberg method only");
         HIP_TRY(hipMemcpy(W, sv->ka.W, sizeof(double) * (size_t)k * k, hipMemcpyDeviceToHost));
@@ -1212,8 +1301,9 @@ hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g)
     if (st) return st;
     const int k = sv->prm.k;
     std::vector<int> buf(k + 1);
+    const size_t ro = (size_t)sv->sel * sv->region;
     if (t) {
-        HIP_TRY(hipMemcpy(buf.data(), sv->ka.tp, sizeof(int) * (k + 1), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(buf.data(), (const char*)sv->ka.tp + ro, sizeof(int) * (k + 1), hipMemcpyDeviceToHost));
         for (int i = 0; i <= k; ++i) t[i] = i < sv->nt ? buf[i] : -1;
     }
     if (g) {
@@ -1229,7 +1319,8 @@ hk_status hk_solve_get_residuals(hk_solve* sv, double* res)
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (!res) return fail(HK_EINVAL, "null output");
-    HIP_TRY(hipMemcpy(res, sv->la.res, sizeof(double) * sv->prm.k, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(res, (const char*)sv->la.res + (size_t)sv->sel * sv->region, sizeof(double) * sv->prm.k,
+                      hipMemcpyDeviceToHost));
     for (int i = sv->k_done; i < sv->prm.k; ++i) res[i] = 0.0;
     return HK_OK;
 }
@@ -1240,9 +1331,11 @@ hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c)
     if (st) return st;
     // the small problem's inputs (for the unsketched method H, [I; 0], beta e_1)
     const size_t sk = (size_t)sv->prm.s * sv->prm.k;
-    if (Z) HIP_TRY(hipMemcpy(Z, sv->la.Z, sizeof(double) * sk, hipMemcpyDeviceToHost));
-    if (F) HIP_TRY(hipMemcpy(F, sv->la.F, sizeof(double) * sk, hipMemcpyDeviceToHost));
-    if (c) HIP_TRY(hipMemcpy(c, sv->la.c, sizeof(double) * sv->prm.s, hipMemcpyDeviceToHost));
+    const size_t ro = (size_t)sv->sel * sv->region;
+    if (Z) HIP_TRY(hipMemcpy(Z, (const char*)sv->la.Z + ro, sizeof(double) * sk, hipMemcpyDeviceToHost));
+    if (F) HIP_TRY(hipMemcpy(F, (const char*)sv->la.F + ro, sizeof(double) * sk, hipMemcpyDeviceToHost));
+    if (c) HIP_TRY(hipMemcpy(c, sv->la.c + (size_t)sv->sel * sv->la.c_stride, sizeof(double) * sv->prm.s,
+                             hipMemcpyDeviceToHost));
     return HK_OK;
 }
 
@@ -1253,14 +1346,16 @@ hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev)
     if (!dst_dev) return fail(HK_EINVAL, "null output");
     const size_t es = dsize(sv->tb);
     const int kp1 = sv->prm.k + 1;
+    // the selected right-hand side's basis and scales
+    const void* Lb = (const char*)sv->ka.L + es * (size_t)sv->sel * kp1 * (size_t)sv->ka.ldl;
+    const double* scb = (const double*)((const char*)sv->ka.scale + (size_t)sv->sel * sv->region);
     if (which == 2 || (which == 0 && sv->kernel != OP_BLUR_ONEBAR)) {
         // the columns as stored (unnormalised v_j for the single-barrier kernel)
-        HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->n, sv->ka.L, es * sv->ka.ldl, es * sv->op->n, kp1,
+        HIP_TRY(hipMemcpy2D(dst_dev, es * sv->op->n, Lb, es * sv->ka.ldl, es * sv->op->n, kp1,
                             hipMemcpyDeviceToDevice));
     } else if (which == 0) {
         // stored unnormalised with per-column scales: copy l_j = s_j v_j
-        HIP_TRY(launch_scale_basis(sv->tb, sv->ka.L, sv->ka.ldl, sv->ka.scale, sv->op->n, kp1, dst_dev,
-                                   sv->stream));
+        HIP_TRY(launch_scale_basis(sv->tb, Lb, sv->ka.ldl, scb, sv->op->n, kp1, dst_dev, sv->stream));
         HIP_TRY(hipStreamSynchronize(sv->stream));
     } else if (which == 1) {
         if (!sv->rect) return fail(HK_EINVAL, "D exists for the generalized Hessenberg method only");

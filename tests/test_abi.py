@@ -37,7 +37,7 @@ def test_library_exports_every_header_function(hk):
 
 def test_version_and_null_argument_errors(hk):
     L = hk.lib()
-    assert hk.hk_abi_version() == 1
+    assert hk.hk_abi_version() == 2
     assert L.hk_solve_wait(None) == hk.HK_EINVAL
     assert "null" in hk.hk_last_error()
     assert L.hk_op_destroy(None) == hk.HK_EINVAL
@@ -46,6 +46,8 @@ def test_version_and_null_argument_errors(hk):
     assert L.hk_op_create_blur(None, 4, 4, None, None, 1, 0, 0, None) == hk.HK_EINVAL
     assert L.hk_solve_create(None, None, None) == hk.HK_EINVAL
     assert L.hk_solve_grid(None, None) == hk.HK_EINVAL
+    assert L.hk_solve_select_rhs(None, 0) == hk.HK_EINVAL
+    assert L.hk_solve_run_noalloc(None, None, None, None, None) == hk.HK_EINVAL
     # the serving loop: null handles are refused before any device work
     assert L.hk_server_create(None, 4, 0, 0, None) == hk.HK_EINVAL
     assert L.hk_server_destroy(None) == hk.HK_EINVAL

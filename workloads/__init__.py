@@ -291,6 +291,20 @@ def blur_problem(name, ny, nx, sigma, radius, bc, phantom, eta, k, s, lam, sketc
                    psf=psf)
 
 
+def blur_rhs_family(P: Problem, nr: int, eta: float = 0.02) -> list:
+    """nr deblurring problems on P's (separable) blur operator: P itself,
+    then piecewise-smooth phantoms and noise drawn from seeds 17 r past P's,
+    blurred by the same operator (several right-hand sides of one operator)."""
+    out = [P]
+    for r in range(1, nr):
+        rng = np.random.default_rng(PHANTOM_SEED + 17 * r)
+        x = phantom_piecewise(P.ny, P.nx, rng)
+        clean = blur_apply_scipy(x, P.taps_y, P.taps_x, P.bc, psf=P.psf)
+        b = add_noise(clean, eta, np.random.default_rng(NOISE_SEED + 17 * r)).ravel()
+        out.append(P.replace(b=b, x_true=x.ravel().copy()))
+    return out
+
+
 def csr_problem(name, N, n_angles, n_bins, eta, k, s, lam, sketch, zeta=8, dtype="f32",
                 cfg_id=0, phantom_seed=PHANTOM_SEED, noise_seed=NOISE_SEED) -> Problem:
     import scipy.sparse as sp
