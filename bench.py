@@ -80,6 +80,55 @@ def algorithmic_bytes(n: int, k: int, w: int) -> int:
     return sum((j + 1) * n * w for j in range(1, k + 1))
 
 
+def algorithmic_bytes_csr(P, k: int, w: int) -> int:
+    # rectangular process, step j (1..k): u = A l_j and q = A^T d_{j+1} each
+    # stream the operator's column indices (int32) and values once; the two
+    # eliminations read d_1..d_j and l_1..l_j (l_j is also the input of A) and
+    # write d_{j+1} and l_{j+1}: (j + 1)(m + n) w bytes.  Row pointers are
+    # staged in LDS once per solve and not counted.
+    vb = 4 if P.dtype == "f32" else 8
+    nnz = int(P.rowptr[-1])
+    return sum(2 * nnz * (4 + vb) + (j + 1) * (P.m + P.n) * w for j in range(1, k + 1))
+
+
+def csr_line(hk, ctx, steps: int, warmup: int):
+    """The CSR tomography workload (256x256 image, 180 angles x 362 bins,
+    k = 150, Gaussian s = 302, FP32 operator and data, FP64 bases): its solve
+    time and the generic kernel's algorithmic bandwidth."""
+    import torch
+    import workloads as W
+    P = W.config("c3")
+    op = hk.Operator.csr(ctx, P.m, P.n, P.rowptr, P.col, P.val.astype(np.float32), hk.HK_F32)
+    sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, basis_dtype=hk.HK_F64)
+    b = torch.tensor(P.b.astype(np.float32), device="cuda:0")
+    x = torch.empty(P.n, dtype=torch.float32, device="cuda:0")
+    for _ in range(warmup):
+        sv.run(b, x)
+    sv.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sv.run(b, x)
+    st = sv.wait()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kd = sv.k_done()
+    it_ms, tot_ms = sv.timing_history(steps)
+    alg = algorithmic_bytes_csr(P, kd, 8)
+    iter_avg = float(np.mean(it_ms))
+    achieved = alg / (iter_avg * 1e-3) / 1e9
+    sv.close()
+    op.close()
+    print(f"# csr tomography: {wall * 1e3 / steps:.3f} ms per solve", file=sys.stderr, flush=True)
+    return {"workload": f"tomography 256x256, 180 angles x 362 bins (m={P.m}, n={P.n}, nnz={int(P.rowptr[-1])}), "
+                        "k=150, Gaussian s=302, lambda=0, FP32 operator, FP64 bases",
+            "status": st, "k": kd, "ms_per_solve": round(wall * 1e3 / steps, 4),
+            "hessenberg_iters_per_s": round(kd * steps / wall, 1),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(achieved / PEAK_HBM_GBS, 4), "kernel": "iterate_kernel (generic, CSR)",
+                         "alg_bytes_per_launch": alg, "avg_launch_ms": round(iter_avg, 4)}}
+
+
 def cpu_baseline(P, max_seconds: float = 30.0):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -217,6 +266,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--workload", default="c2", help=argparse.SUPPRESS)
+    ap.add_argument("--no-csr", dest="csr", action="store_false", help="skip the CSR tomography line")
     ap.add_argument("--rhs", type=int, default=4, help="right-hand sides of the multi-right-hand-side line (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run only a plain device copy of BYTES (counter calibration)")
@@ -265,7 +315,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     iters = k_done * args.steps
     value = iters / wall
-    alg = algorithmic_bytes(P.n, k_done, w) if P.kind == "blur" else None
+    alg = algorithmic_bytes(P.n, k_done, w) if P.kind == "blur" else algorithmic_bytes_csr(P, k_done, w)
     iter_avg = float(np.mean(it_ms))
     roof = None
     if alg is not None:
@@ -273,7 +323,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": measured_traffic() if args.workload == "c2" else None,
-                "kernel": "blur_iterate_kernel (persistent basis iteration)",
+                "kernel": ("blur_iterate_kernel (persistent basis iteration)" if P.kind == "blur"
+                           else "iterate_kernel (generic, CSR)"),
                 "alg_bytes_per_launch": alg, "avg_launch_ms": round(iter_avg, 4)}
     out = {
         "metric": "Hessenberg iters/s + HBM GB/s at 512² deblur; solves/s with p50/p99 latency",
@@ -298,6 +349,8 @@ def main():
                        "p99": round(float(np.percentile(tot_ms, 99)), 4)},
         "roofline": roof,
     }
+    if args.csr and args.workload == "c2":
+        out["csr_tomography"] = csr_line(hk, ctx, 5, 2)
     if args.rhs > 0:
         out["multi_rhs"] = multi_rhs(hk, ctx, args.rhs, max(3, args.steps // 2), 2)
     if args.serve_requests > 0:

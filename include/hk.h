@@ -225,6 +225,20 @@ hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* params, siz
  * The solve can be run many times (each run overwrites its results). */
 hk_status hk_solve_create(hk_op* op, const hk_params* params, hk_solve** out);
 
+/* Create a solve on a workspace the caller owns (for callers that manage
+ * device memory themselves: pools, arenas, one allocation shared by several
+ * solves run one after another).  ws_dev: NULL, then this is hk_solve_create;
+ * else a device pointer on the op's device, 256-byte aligned, to at least
+ * ws_bytes >= hk_solve_workspace_bytes(op, params) bytes.  The caller keeps
+ * it alive, and touches it with nothing else, until hk_solve_destroy; the
+ * library never frees it.  It is cleared here by a kernel on the context
+ * stream (nothing must start at particular values).  The library still
+ * allocates the host handle and its timing events.  Errors: HK_EINVAL for a
+ * misaligned pointer, HK_ENOMEM when ws_bytes is too small; the rest as
+ * hk_solve_create. */
+hk_status hk_solve_create_with_workspace(hk_op* op, const hk_params* params, void* ws_dev, size_t ws_bytes,
+                                         hk_solve** out);
+
 /* Run: enqueue the whole solve on the context stream and return at once.
  * b_dev: device array of the op's dtype, m x nrhs column-major (right-hand
  * side r at b_dev + r m; read during the run).  x_dev: n x nrhs likewise
@@ -286,6 +300,18 @@ hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g);
 hk_status hk_solve_get_residuals(hk_solve* sv, double* res);
 hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c);
 hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev);
+
+/* The solution after the first kp basis vectors, 1 <= kp <= k_done, of the
+ * selected right-hand side: x_kp = L_kp y_kp with y_kp the minimiser of the
+ * small problem of eq. (sketched_LSLU) (eq. (sketched_LSLU_hybrid) when
+ * lambda > 0) over the first kp columns.  The factors of the full small
+ * problem already hold it (the leading kp x kp block of its triangular
+ * factor and the first kp rotated right-hand-side entries), so no new
+ * factorisation is done; its objective value is res[kp-1] above, and
+ * kp = k_done gives the run's x bit for bit.  x_dev: device array of n
+ * elements of the op's dtype.  Runs on the context stream and returns once
+ * x_dev is written.  Errors: HK_EINVAL for kp outside [1, k_done]. */
+hk_status hk_solve_get_prefix_solution(hk_solve* sv, int32_t kp, void* x_dev);
 
 /* Workgroups of the solve's basis kernel (its grid; one per tile). */
 hk_status hk_solve_grid(const hk_solve* sv, int32_t* workgroups);

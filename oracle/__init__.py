@@ -181,6 +181,19 @@ def small_ls(Z: np.ndarray, F, lam: float, c: np.ndarray):
     return y, res
 
 
+def prefix_solution(o: dict, kp: int, lam: float) -> np.ndarray:
+    """x after the first kp basis vectors of a finished oracle solve (run with
+    keep_basis): the small problem of eq. (sketched_LSLU) /
+    eq. (sketched_LSLU_hybrid) restricted to the first kp columns of Z and F,
+    solved afresh by the Householder routine above, then x = L_kp y.  The
+    Hessenberg process for kp steps is the prefix of the one for k steps, so
+    this is the solve that stops after kp steps."""
+    if not 1 <= kp <= o["k_done"]:
+        raise ValueError(f"prefix length {kp} outside [1, {o['k_done']}]")
+    y, _ = small_ls(o["Z"][:, :kp], o["F"][:, :kp], lam, o["c"])
+    return o["Lmat"][:, :kp] @ y
+
+
 def solve(problem, k=None, s=None, lam=None, method=None, keep_basis=False, seed=None):
     """Run sCMRH (square) or sLSLU (rectangular) on a ``workloads.Problem``.
 

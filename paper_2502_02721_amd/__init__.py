@@ -36,10 +36,11 @@ ABI_FUNCTIONS = (
     "hk_abi_version", "hk_last_error", "hk_context_create", "hk_context_destroy",
     "hk_op_create_blur", "hk_op_create_gaussian_blur", "hk_op_create_blur_psf", "hk_op_create_csr", "hk_op_shape",
     "hk_op_apply", "hk_op_destroy", "hk_solve_workspace_bytes", "hk_solve_create",
+    "hk_solve_create_with_workspace",
     "hk_solve_run", "hk_solve_run_noalloc", "hk_solve_wait", "hk_solve_info", "hk_solve_select_rhs",
     "hk_solve_get_hessenberg",
     "hk_solve_get_pivots", "hk_solve_get_residuals", "hk_solve_get_sketches",
-    "hk_solve_get_basis", "hk_solve_timing", "hk_solve_grid", "hk_solve_timing_history", "hk_solve_get_trace",
+    "hk_solve_get_basis", "hk_solve_get_prefix_solution", "hk_solve_timing", "hk_solve_grid", "hk_solve_timing_history", "hk_solve_get_trace",
     "hk_solve_destroy", "hk_server_create", "hk_server_destroy", "hk_server_submit", "hk_server_poll",
     "hk_server_wait", "hk_server_result",
 )
@@ -84,6 +85,7 @@ def lib():
             "hk_op_destroy": ([vp], st),
             "hk_solve_workspace_bytes": ([vp, C.POINTER(hk_params), C.POINTER(C.c_size_t)], st),
             "hk_solve_create": ([vp, C.POINTER(hk_params), pp], st),
+            "hk_solve_create_with_workspace": ([vp, C.POINTER(hk_params), vp, C.c_size_t, pp], st),
             "hk_solve_run": ([vp, vp, vp], st),
             "hk_solve_run_noalloc": ([vp, C.POINTER(hk_params), vp, vp, vp], st),
             "hk_solve_wait": ([vp], st),
@@ -94,6 +96,7 @@ def lib():
             "hk_solve_get_residuals": ([vp, vp], st),
             "hk_solve_get_sketches": ([vp, vp, vp, vp], st),
             "hk_solve_get_basis": ([vp, i32, vp], st),
+            "hk_solve_get_prefix_solution": ([vp, i32, vp], st),
             "hk_solve_timing": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double)], st),
             "hk_solve_grid": ([vp, C.POINTER(C.c_int32)], st),
             "hk_solve_timing_history": ([vp, i32, vp, vp, C.POINTER(i32)], st),
@@ -211,6 +214,13 @@ def hk_solve_workspace_bytes(op, params: hk_params) -> int:
 def hk_solve_create(op, params: hk_params) -> int:
     h = C.c_void_p()
     _check(lib().hk_solve_create(C.c_void_p(op), C.byref(params), C.byref(h)))
+    return h.value
+
+
+def hk_solve_create_with_workspace(op, params: hk_params, ws_ptr: int, ws_bytes: int) -> int:
+    h = C.c_void_p()
+    _check(lib().hk_solve_create_with_workspace(C.c_void_p(op), C.byref(params), C.c_void_p(ws_ptr),
+                                                C.c_size_t(ws_bytes), C.byref(h)))
     return h.value
 
 
@@ -413,7 +423,11 @@ class Solve(_Owner):
     """A solve of one operator with fixed parameters; run() may be called repeatedly."""
 
     def __init__(self, op: Operator, k, s, lam=0.0, sketch=HK_SKETCH_GAUSSIAN, zeta=8, seed=0,
-                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0, pivot_sample=0, max_workgroups=0, nrhs=1):
+                 method=HK_METHOD_AUTO, basis_dtype=None, flags=0, pivot_sample=0, max_workgroups=0, nrhs=1,
+                 workspace=None):
+        """workspace: None (the library allocates), or a device tensor the
+        caller owns, of at least workspace_bytes() bytes; it is kept alive
+        by this object."""
         self.op = op
         if basis_dtype is None:
             basis_dtype = op.dtype
@@ -424,7 +438,12 @@ class Solve(_Owner):
         # without a sketch the small problem is H_{k+1,k}: s is taken as k + 1
         self.k, self.s = k, (k + 1 if sketch == HK_SKETCH_NONE else s)
         self.rect = (method == HK_METHOD_CHANGING_HESSENBERG) or (method == HK_METHOD_AUTO and op.m != op.n)
-        self.handle = hk_solve_create(op.handle, self.params)
+        if workspace is None:
+            self.handle = hk_solve_create(op.handle, self.params)
+        else:
+            nb = workspace.numel() * workspace.element_size()
+            self.handle = hk_solve_create_with_workspace(op.handle, self.params, workspace.data_ptr(), nb)
+        self._ws = workspace
         self._init_owner(op)
 
     def _destroy(self):
@@ -474,6 +493,16 @@ class Solve(_Owner):
         out = torch.empty((self.k + 1, length), dtype=tdt, device=f"cuda:{self.op.ctx.device}")
         hk_solve_get_basis(self.handle, which, out.data_ptr())
         return out   # row i = basis vector i
+
+    def prefix_solution(self, kp: int, out=None):
+        """x after the first kp basis vectors (1 <= kp <= k_done), from the
+        run's own small-problem factors."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.op.n, dtype=self.op.torch_dtype(), device=f"cuda:{self.op.ctx.device}")
+        self.op._vec(out, self.op.n, "x")
+        _check(lib().hk_solve_get_prefix_solution(C.c_void_p(self.handle), kp, C.c_void_p(out.data_ptr())))
+        return out
 
     def timing(self):
         return hk_solve_timing(self.handle)

@@ -199,6 +199,7 @@ struct CombineArgs {
     // right-hand side blockIdx.y: its basis (k + 1) columns further on, x n
     // elements further on, y, scale and ctl rhs_stride bytes further on
     long long rhs_stride;
+    int kcap;                    // > 0: use at most kcap columns (a prefix solution)
 };
 
 struct ApplyArgs {
@@ -221,6 +222,11 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);   // p, byte
 hipError_t launch_solve_info(const Ctl* ctl, int32_t* info, hipStream_t st);
 hipError_t launch_small_ls(const LsArgs& a, hipStream_t st);
 hipError_t launch_combine(int tb, int to, const CombineArgs& a, int nrhs, hipStream_t st);
+// y' = R(1:kp, 1:kp)^{-1} d(1:kp) (R column-major with leading dimension k),
+// by the same column-oriented substitution as the least-squares kernels
+// (recip: multiply by the reciprocal of the diagonal, as the blocked kernel)
+hipError_t launch_prefix_y(const double* R, const double* d, int k, int kp, int recip, double* yp,
+                           hipStream_t st);
 // block sketch C = S B with S generated (hk_bsk.hip)
 struct BskArgs {
     const void* q;              // B: len x ncol, column-major, leading dimension ldq

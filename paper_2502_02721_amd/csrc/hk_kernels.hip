@@ -127,7 +127,8 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a)
     const double* y = (const double*)((const char*)a.y + st_b);
     const double* scale = a.scale ? (const double*)((const char*)a.scale + st_b) : nullptr;
     const int st = ctl->status;
-    const int kd = (st < 0) ? 0 : ctl->k_done;
+    int kd = (st < 0) ? 0 : ctl->k_done;
+    if (a.kcap > 0) kd = min(kd, a.kcap);
     double acc = 0.0;
     if (scale) {
         for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], y[j] * scale[j], acc);
@@ -320,6 +321,37 @@ hipError_t launch_combine(int tb, int to, const CombineArgs& a, int nrhs, hipStr
     else if (tb == 2 && to == 1) hipLaunchKernelGGL((combine_kernel<__bf16, float>), dim3(blocks), dim3(256), 0, st, a);
     else if (tb == 3 && to == 1) hipLaunchKernelGGL((combine_kernel<_Float16, float>), dim3(blocks), dim3(256), 0, st, a);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Prefix solution of the small problem: with [Z; lambda F] = Q R, the first
+// kp columns have the factors Q(:, 1:kp), R(1:kp, 1:kp), so
+// y_kp = R(1:kp, 1:kp)^{-1} d(1:kp), d = Q^T [c; 0] (eq. (sketched_LSLU),
+// eq. (sketched_LSLU_hybrid) restricted to the first kp basis vectors).
+// One wave, column-oriented like the least-squares kernels' substitution.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void prefix_y_kernel(const double* R, const double* d, int k, int kp, int recip,
+                                                      double* yp)
+{
+    __shared__ double dl[256];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < kp; i += 64) dl[i] = d[i];
+    __syncthreads();
+    for (int i = kp - 1; i >= 0; --i) {
+        const double rii = R[(long long)i * k + i];
+        const double yi = recip ? dl[i] * (1.0 / rii) : dl[i] / rii;
+        __syncthreads();
+        if (lane == 0) yp[i] = yi;
+        for (int q = lane; q < i; q += 64) dl[q] = fma(-R[(long long)i * k + q], yi, dl[q]);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_prefix_y(const double* R, const double* d, int k, int kp, int recip, double* yp, hipStream_t st)
+{
+    if (kp < 1 || kp > k || k > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(prefix_y_kernel, dim3(1), dim3(64), 0, st, R, d, k, kp, recip, yp);
     return hipGetLastError();
 }
 

@@ -134,6 +134,7 @@ struct hk_solve {
     int nrhs = 1;                          // right-hand sides advanced together
     int sel = 0;                           // the one the getters report
     double* call = nullptr;                // S2 b of the first right-hand side (the others follow)
+    double* yp = nullptr;                  // prefix-solution coefficients (first right-hand side's region)
     size_t region = 0;                     // bytes between right-hand sides' regions
     double* T = nullptr;
     double* T1 = nullptr;
@@ -474,7 +475,7 @@ hk_params effective_params(const hk_params& p)
 
 struct WsLayout {
     size_t ctl, L, D, H, W, tp, gp, PD, PL, pvD, pvL, amv, ami, zpart, fpart, cpart, Z, F, c;
-    size_t Q, R, r, y, res, d, trace, scale, wpart, sval, sidx, T, T1, call, part, total;
+    size_t Q, R, r, y, yp, res, d, trace, scale, wpart, sval, sidx, T, T1, call, part, total;
     size_t region;          // bytes of one right-hand side's region (regions first, side by side)
     int trace_cap;
     int64_t ldl, ldd;
@@ -515,6 +516,7 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
     w.R = take(sizeof(double) * (size_t)k * k);
     w.r = take(sizeof(double) * rows);
     w.y = take(sizeof(double) * k);
+    w.yp = take(sizeof(double) * k);
     w.res = take(sizeof(double) * k);
     w.d = take(sizeof(double) * k);
     w.trace_cap = (p->flags & HK_FLAG_TRACE) ? 2 * (6 * kp1 + 8) + 16 * (kp1 + 1) : 0;
@@ -1038,6 +1040,7 @@ static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rec
     l.R = (double*)(base + w.R);
     l.r = (double*)(base + w.r);
     l.y = (double*)(base + w.y);
+    sv->yp = (double*)(base + w.yp);
     l.res = (double*)(base + w.res);
     l.d = (double*)(base + w.d);
     l.ctl = a.ctl;
@@ -1153,6 +1156,15 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
 {
     if (!op) return fail(HK_EINVAL, "null operator");
     return solve_create(op, p, nullptr, 0, hk_solve::NEV, op->ctx->stream, out);
+}
+
+hk_status hk_solve_create_with_workspace(hk_op* op, const hk_params* p, void* ws_dev, size_t ws_bytes,
+                                         hk_solve** out)
+{
+    if (!op) return fail(HK_EINVAL, "null operator");
+    if (ws_dev && ((uintptr_t)ws_dev & 255)) return fail(HK_EINVAL, "workspace pointer is not 256-byte aligned");
+    if (ws_dev && ws_bytes == 0) return fail(HK_ENOMEM, "workspace of 0 bytes");
+    return solve_create(op, p, ws_dev, ws_bytes, hk_solve::NEV, op->ctx->stream, out);
 }
 
 hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
@@ -1322,6 +1334,30 @@ hk_status hk_solve_get_residuals(hk_solve* sv, double* res)
     HIP_TRY(hipMemcpy(res, (const char*)sv->la.res + (size_t)sv->sel * sv->region, sizeof(double) * sv->prm.k,
                       hipMemcpyDeviceToHost));
     for (int i = sv->k_done; i < sv->prm.k; ++i) res[i] = 0.0;
+    return HK_OK;
+}
+
+hk_status hk_solve_get_prefix_solution(hk_solve* sv, int32_t kp, void* x_dev)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    if (!x_dev) return fail(HK_EINVAL, "null output");
+    if (kp < 1 || kp > sv->k_done) return fail(HK_EINVAL, "prefix length %d outside [1, %d]", kp, sv->k_done);
+    HIP_TRY(hipSetDevice(sv->op->ctx->device));
+    const hipStream_t s = sv->op->ctx->stream;
+    const size_t ro = (size_t)sv->sel * sv->region;
+    auto at = [&](auto* q) { return (decltype(q))((char*)q + ro); };
+    double* yp = at(sv->yp);
+    HIP_TRY(launch_prefix_y(at(sv->la.R), at(sv->la.d), sv->prm.k, kp, sv->la.nb > 0 ? 1 : 0, yp, s));
+    CombineArgs c = sv->ca;
+    c.L = (const char*)c.L + (size_t)sv->sel * (sv->prm.k + 1) * c.ldl * dsize(sv->prm.basis_dtype);
+    c.ctl = at(c.ctl);
+    c.y = yp;
+    c.scale = c.scale ? at(c.scale) : nullptr;
+    c.x = x_dev;
+    c.kcap = kp;
+    HIP_TRY(launch_combine(sv->tb, sv->op->dtype, c, 1, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return HK_OK;
 }
 

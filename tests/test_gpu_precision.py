@@ -172,7 +172,7 @@ def test_precision_tier_small(hk, ctx, orc, basis, sketch):
 def c2_fp64(orc):
     P = W.config("c2")
     _flush("FP64 oracle on the 512x512 deblurring workload")
-    return P, orc.solve(rounded_problem(P))
+    return P, orc.solve(rounded_problem(P), keep_basis=True)
 
 
 @pytest.mark.parametrize("basis", ["f32", "bf16", "f16"])
@@ -184,6 +184,60 @@ def test_precision_tier_deblur512(hk, ctx, orc, c2_fp64, basis):
     check_stored_basis(orc, P, g, basis)
     report_vs_fp64(P, g, o64, basis)
     _flush(f"  {basis}: basis kernel {g['iter_ms']:.3f} ms, solve {g['total_ms']:.3f} ms")
+
+
+def test_precision_tier_per_iteration_deblur512(hk, ctx, orc, c2_fp64):
+    """The error of each storage type against the FP64 oracle after every
+    tenth step: relative error of x_k' against the oracle's x_k' (both the
+    minimiser over the first k' basis vectors), against x_true, the sketched
+    objective res[k'-1] and the true relative residual ||b - A x_k'|| / ||b||
+    (FP64 on the host).  Written as JSON lines to $HK_PRECISION_REPORT when
+    set.  Bounded loosely, as the final solution: the reconstruction error of
+    every x_k' may exceed the FP64 oracle's by at most MARGIN."""
+    import json
+    import os
+    import torch
+    P, o64 = c2_fp64
+    kps = list(range(10, P.k + 1, 10))
+    b64 = P.b.astype(np.float32).astype(np.float64)
+    nb = np.linalg.norm(b64)
+
+    def true_res(x):
+        return np.linalg.norm(b64 - W.blur_apply_scipy(x.reshape(P.ny, P.nx), P.taps_y, P.taps_x, P.bc).ravel()) / nb
+
+    x64 = {kp: orc.prefix_solution(o64, kp, P.lam) for kp in kps}
+    rows = []
+    for basis in ("f32", "bf16", "f16"):
+        op = make_operator(hk, ctx, P)
+        sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, 0, basis_dtype=_bdt(hk, basis))
+        try:
+            b = torch.tensor(P.b.astype(np.float32), device=f"cuda:{ctx.device}")
+            sv.run(b)
+            assert sv.wait() == 0 and sv.k_done() == P.k
+            res = sv.residuals()
+            for kp in kps:
+                x = sv.prefix_solution(kp).cpu().numpy().astype(np.float64)
+                row = {"basis": basis, "k": kp, "err_vs_fp64": rel(x, x64[kp]),
+                       "err_vs_true": rel(x, P.x_true), "fp64_err_vs_true": rel(x64[kp], P.x_true),
+                       "sketched_res": float(res[kp - 1]), "fp64_sketched_res": float(o64["res"][kp - 1]),
+                       "true_res": true_res(x), "fp64_true_res": true_res(x64[kp])}
+                rows.append(row)
+                _flush(f"  {basis} k'={kp:3d}: vs FP64 {row['err_vs_fp64']:.3e}  vs x_true {row['err_vs_true']:.4f} "
+                       f"(FP64 {row['fp64_err_vs_true']:.4f})  sketched res {row['sketched_res']:.4e} "
+                       f"(FP64 {row['fp64_sketched_res']:.4e})  true res {row['true_res']:.4e} "
+                       f"(FP64 {row['fp64_true_res']:.4e})")
+        finally:
+            sv.close()
+            op.close()
+    path = os.environ.get("HK_PRECISION_REPORT")
+    if path:
+        with open(path, "w") as f:
+            for row in rows:
+                f.write(json.dumps(row) + "\n")
+    for row in rows:
+        assert row["err_vs_true"] <= row["fp64_err_vs_true"] + MARGIN[row["basis"]], row
+        if row["basis"] == "f32":
+            assert row["err_vs_fp64"] <= 1e-4, row
 
 
 def test_precision_tier_rejects(hk, ctx):
