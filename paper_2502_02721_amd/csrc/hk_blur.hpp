@@ -425,7 +425,7 @@ __global__ __launch_bounds__(NT) void blur_iterate_kernel(KArgs a0)
         // wave 0: h by forward substitution, then h_i s_i and column j of H
         auto coef_solve_wave = [&]() {
             mark(j, 5);
-            forward_subst<TP>(Pl, k, pv, j + 1, h_l);
+            forward_subst_seg<TP>(Pl, k, pv, j + 1, h_l);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -1001,6 +1001,70 @@ __device__ __forceinline__ void forward_subst_nq(const TS* __restrict__ Pl, int 
     }
 }
 
+template <typename TS, int NQ>
+__device__ __forceinline__ void forward_subst_seg_nq(const TS* __restrict__ Pl, int k, const double* __restrict__ pv,
+                                                     int nh, double* h)
+{
+    // The same column-oriented substitution as forward_subst_nq, arranged for
+    // the one-barrier kernel's wave 0.  After h_c is final (lane c & 63 of lane group c >> 6),
+    // every later row takes v_i -= P(i, c) h_c.  The columns run in segments
+    // of 64, one per lane group, unrolled at compile time: h_c is read from a
+    // fixed register, and the groups above the segment (rows all final) take
+    // neither loads nor updates.  Only the segment's own group masks its
+    // rows i <= c (fma(-0, h, v) == v for finite h, so the arithmetic of
+    // every row is the same as with all rows updated).  Rows i >= nh hold
+    // whatever the unused part of the block gives them (LDS is not cleared:
+    // possibly Inf or NaN) and are never read back; the columns c >= nh - 1
+    // past the end, run by the last group of D, take h_c = 0, so they leave
+    // every row i < nh as it is.  The LDS loads of the next D columns are
+    // issued while the current D run.
+    constexpr int D = (NQ <= 1) ? 16 : ((NQ == 2) ? 8 : 4);   // columns in flight (divides 64)
+    const int lane = threadIdx.x & 63;
+    const int plast = (int)packed_size(k) - 1;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        v[q] = (i < nh) ? pv[i] : 0.0;
+    }
+    // slot d of the ring holds column c0 + d as loaded (address clamped, so
+    // the loads never become branches), refilled with column c0 + d + D
+    auto load = [&](int c, TS (&dst)[NQ], int q0) {
+        const int base = packed_col(c, k) - (c + 1);     // base + i = position of P(i, c)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q >= q0) dst[q] = Pl[min(max(base + lane + 64 * q, 0), plast)];
+    };
+    TS ring[D][NQ];
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(d, ring[d], 0);
+#pragma unroll
+    for (int qc = 0; qc < NQ; ++qc) {
+        const int cend = min(64 * qc + 64, nh - 1);
+        for (int c0 = 64 * qc; c0 < cend; c0 += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int c = c0 + d;
+                const double hr = readlane_d(v[qc], c & 63);
+                const double hc = (c < nh - 1) ? hr : 0.0;     // uniform select
+#pragma unroll
+                for (int q = qc; q < NQ; ++q) {
+                    TS pc = ring[d][q];
+                    if (q == qc) pc = (lane > (c & 63)) ? pc : (TS)0;
+                    v[q] = fma(-(double)pc, hc, v[q]);
+                }
+                load(c + D, ring[d], qc);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        if (i < nh) h[i] = v[q];
+    }
+}
+
+// the generic kernel's form (fewer registers: it runs beside the CSR state)
 template <typename TS>
 __device__ __forceinline__ void forward_subst(const TS* __restrict__ Pl, int k, const double* __restrict__ pv,
                                               int nh, double* h)
@@ -1010,6 +1074,17 @@ __device__ __forceinline__ void forward_subst(const TS* __restrict__ Pl, int k, 
     else if (nq == 2) forward_subst_nq<TS, 2>(Pl, k, pv, nh, h);
     else if (nq == 3) forward_subst_nq<TS, 3>(Pl, k, pv, nh, h);
     else forward_subst_nq<TS, 4>(Pl, k, pv, nh, h);
+}
+
+template <typename TS>
+__device__ __forceinline__ void forward_subst_seg(const TS* __restrict__ Pl, int k, const double* __restrict__ pv,
+                                                  int nh, double* h)
+{
+    const int nq = (nh + 63) >> 6;
+    if (nq <= 1) forward_subst_seg_nq<TS, 1>(Pl, k, pv, nh, h);
+    else if (nq == 2) forward_subst_seg_nq<TS, 2>(Pl, k, pv, nh, h);
+    else if (nq == 3) forward_subst_seg_nq<TS, 3>(Pl, k, pv, nh, h);
+    else forward_subst_seg_nq<TS, 4>(Pl, k, pv, nh, h);
 }
 
 // Copy row i (entries c < i) of the row-major global pivot block into the

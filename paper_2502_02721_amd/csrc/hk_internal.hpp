@@ -64,6 +64,7 @@ struct Ctl {
     CtlLine xcnt[16];    // arrivals per XCD
     CtlLine xflag[16];   // release epoch per XCD
     CtlLine pop[16];     // workgroups per XCD
+    CtlLine lsb;         // arrivals at the least-squares kernel's barrier (row-split form)
 };
 
 // Everything the persistent Hessenberg kernel needs (passed by value).
@@ -167,6 +168,12 @@ struct LsArgs {
     int nrhs;
     long long rhs_stride;
     long long c_stride;
+    // row-split form: nwg workgroups per right-hand side, each holding a
+    // slice of the rows; sums over rows meet in xpart (2 x nwg x ls_xcap(k)
+    // doubles, in the right-hand side's region) behind a bounded barrier
+    int nwg;
+    double* xpart;
+    unsigned long long timeout;
 };
 
 // The small problem of right-hand side b (the workgroup's).
@@ -177,7 +184,7 @@ __device__ __forceinline__ LsArgs ls_rebase(const LsArgs& a0, int b)
     const long long st = (long long)b * a0.rhs_stride;
     auto sh = [&](auto* q) { return q ? (decltype(q))((const char*)q + st) : q; };
     a.Z = sh(a0.Z); a.F = sh(a0.F); a.Q = sh(a0.Q); a.R = sh(a0.R); a.r = sh(a0.r);
-    a.y = sh(a0.y); a.res = sh(a0.res); a.d = sh(a0.d); a.ctl = sh(a0.ctl);
+    a.y = sh(a0.y); a.res = sh(a0.res); a.d = sh(a0.d); a.ctl = sh(a0.ctl); a.xpart = sh(a0.xpart);
     a.c = a0.c + (long long)b * a0.c_stride;
     a.trace = nullptr;
     return a;
@@ -250,7 +257,12 @@ hipError_t launch_scale_basis(int tb, const void* src, int64_t ld, const double*
 hipError_t iterate_occupancy(int tb, int to, int op, int sketch, int ept, int samp, int lds_bytes,
                              int* blocks_per_cu);
 size_t small_ls_lds_bytes(int s, int k, double lam);
-int small_ls_panel(int s, int k, double lam, size_t lds_max);
+constexpr int LS_MWG_MAX = 32;   // workgroups of the row-split least-squares kernel
+// doubles per workgroup of one cross-workgroup sum: a projection block
+// ((k + 1) x 16) or a 16 x 16 Gram matrix
+__host__ __device__ inline int ls_xcap(int k) { return (k + 1) * 16 > 256 ? (k + 1) * 16 : 256; }
+int small_ls_wgs(int s, double lam);
+int small_ls_panel(int s, int k, double lam, int nwg, size_t lds_max);
 hipError_t launch_small_ls_blocked(int nb, const LsArgs& a, hipStream_t st);
 
 }  // namespace hk

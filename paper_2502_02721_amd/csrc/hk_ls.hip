@@ -81,6 +81,63 @@ __device__ __forceinline__ double block_sum1(double v, double* red)
     return t;
 }
 
+// Row-split form: workgroup wg of nwg holds the rows [r0, r1) of M, and a
+// sum over all rows is its partial plus the others', added in workgroup
+// order, so every workgroup gets the same bits and takes the same branches.
+// The partials meet in global memory (double-buffered by call parity: a
+// workgroup cannot write call e + 2's partial before every workgroup has
+// passed call e + 1's barrier, i.e. finished reading call e's) behind a
+// counting barrier on ctl->lsb with the basis kernel's bounded wait.
+struct XSum {
+    double* part;                // 2 x nwg x cap doubles
+    Ctl* ctl;
+    unsigned long long timeout;
+    int nwg, wg, cap;
+    unsigned ep;                 // calls so far
+    bool failed;                 // a barrier wait timed out (abort raised)
+};
+
+// v (LDS, n <= cap doubles, complete at entry) becomes the sum over the
+// workgroups; false after a barrier time-out.
+__device__ bool xsum(XSum& x, double* v, int n)
+{
+    if (x.nwg == 1) return true;
+    double* buf = x.part + (size_t)(x.ep & 1u) * x.nwg * x.cap;
+    for (int e = threadIdx.x; e < n; e += LSB_NT) buf[(size_t)x.wg * x.cap + e] = v[e];
+    ++x.ep;
+    __shared__ int s_xok;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&x.ctl->lsb.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ok = spin_until(&x.ctl->lsb.v, x.ep * (unsigned)x.nwg, x.ctl, x.timeout);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_xok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_xok) {
+        x.failed = true;
+        return false;
+    }
+    // the partials of 8 workgroups are loaded at once (latency, not
+    // bandwidth, bounds this), then added in workgroup order
+    for (int e = threadIdx.x; e < n; e += LSB_NT) {
+        double t = 0.0;
+        for (int w0 = 0; w0 < x.nwg; w0 += 8) {
+            double q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                q[u] = (w0 + u < x.nwg) ? buf[(size_t)(w0 + u) * x.cap + e] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t += q[u];
+        }
+        v[e] = t;
+    }
+    __syncthreads();
+    return true;
+}
+
 // W[c * 16 + p] = sum_i Q[i * QS + c] P[p * RP + i] for c < j0 (MFMA: A = Q^T
 // block, B = P block, K = rows).  Work units: ncb column blocks x nsplit row
 // groups, unit u on wave u % 8; row-group partials are summed in group order
@@ -304,9 +361,10 @@ __device__ __forceinline__ bool chol_rows(double (&r)[PNB], int lane, int nb_)
 //   rcur by Rs rcur.  Returns false (P untouched) when a pivot of the scaled
 //   Gram matrix is below CHOL_TINY.  G, Lm, rcur, rtmp: 256 doubles each.
 __device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, double* Lm, double* sc,
-                             double* rcur, double* rtmp, double* red, int* s_ok, unsigned long long* tr)
+                             double* rcur, double* rtmp, double* red, int* s_ok, unsigned long long* tr, XSum& xs)
 {
     panel_gram(P, R, G, red);
+    if (!xsum(xs, G, 256)) return false;
     lsmark(tr, 0);
     const int RP = panel_ld(R);
     if (threadIdx.x < 64) {
@@ -384,20 +442,32 @@ __device__ bool cholqr_stage(double* P, int R, int nb, bool scale, double* G, do
 template <int NB>
 __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
 {
-    const LsArgs a = ls_rebase(a_in, blockIdx.x);     // one workgroup per right-hand side
+    const LsArgs a = ls_rebase(a_in, blockIdx.y);     // a row of nwg workgroups per right-hand side
     static_assert(NB == PNB, "panel width is the MFMA tile");
+    const int nwg = gridDim.x, wg = blockIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
     // timestamps: slot 0 start, 1 end, 8 + 8 b + id for panel b
     auto mark = [&](int slot) {
         if (a.trace && threadIdx.x == 0 && slot < LS_TRACE) a.trace[slot] = wall_clock64();
     };
-    mark(0);
-    for (int i = threadIdx.x; i < a.k; i += LSB_NT) a.res[i] = 0.0;
+    if (wg == 0) mark(0);
+    if (wg == 0)
+        for (int i = threadIdx.x; i < a.k; i += LSB_NT) a.res[i] = 0.0;
     if (a.ctl->status < 0) return;
     const int kd = a.ctl->k_done;
     if (kd <= 0) return;
     const int s = a.s, k = a.k;
-    const int R = a.lam > 0.0 ? 2 * s : s;
+    const int Rall = a.lam > 0.0 ? 2 * s : s;
+    // this workgroup's rows of M: [g0, g0 + R)
+    const int g0 = (int)(((long long)wg * Rall) / nwg);
+    const int R = (int)(((long long)(wg + 1) * Rall) / nwg) - g0;
+    XSum xs{a.xpart, a.ctl, a.timeout, nwg, wg, ls_xcap(k), 0u, false};
+    auto fail_barrier = [&]() {
+        if (threadIdx.x == 0) {
+            a.ctl->ls_status = -3;
+            if (a.ctl->status == 0) a.ctl->status = -3;
+        }
+    };
     const int ncol = kd + 1;                       // basis columns + right-hand side
     const int RP = panel_ld(R);
     double* P = (double*)smem;                     // NB x R panel, column-major, column stride RP
@@ -412,11 +482,12 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
     double* coef = sc + 16;                        // 16
     double* Rm = a.R;                              // k x k, column-major: Rm[col * k + row]
     double* dv = a.d;
-    double* Q = a.Q;                               // R x k, row-major: Q[i * k + c]
+    double* Q = a.Q + (long long)g0 * k;           // this workgroup's rows, row-major: Q[i * k + c]
     __shared__ double s_rho;
     __shared__ int s_ok;
 
-    for (int e = threadIdx.x; e < kd * k; e += LSB_NT) Rm[e] = 0.0;
+    if (wg == 0)
+        for (int e = threadIdx.x; e < kd * k; e += LSB_NT) Rm[e] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
 
@@ -429,7 +500,7 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
             double v[2][NB];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int i = min(ib + h * LSB_NT + (int)threadIdx.x, R - 1);
+                const int i = g0 + min(ib + h * LSB_NT + (int)threadIdx.x, R - 1);   // row of M
 #pragma unroll
                 for (int p = 0; p < NB; ++p) {
                     const int col = min(j0 + p, kd);
@@ -440,14 +511,15 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int i = ib + h * LSB_NT + (int)threadIdx.x;
+                const int i = ib + h * LSB_NT + (int)threadIdx.x;     // local row
                 if (i < R) {
+                    const int gi = g0 + i;
 #pragma unroll
                     for (int p = 0; p < NB; ++p) {
                         const int col = j0 + p;
                         double x = 0.0;
-                        if (col < kd) x = (i < s) ? v[h][p] : a.lam * v[h][p];
-                        else if (col == kd && i < s) x = v[h][p];
+                        if (col < kd) x = (gi < s) ? v[h][p] : a.lam * v[h][p];
+                        else if (col == kd && gi < s) x = v[h][p];
                         P[p * RP + i] = x;
                     }
                 }
@@ -457,28 +529,30 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
         if (threadIdx.x < 256) rcur[threadIdx.x] = ((threadIdx.x >> 4) == (threadIdx.x & 15)) ? 1.0 : 0.0;
         __syncthreads();
         const int pb = 8 + 8 * (j0 / NB);
-        mark(pb);
+        if (wg == 0) mark(pb);
         // ---- two projections against Q(:, 0 .. j0)
         if (j0 > 0) {
             for (int pass = 0; pass < 2; ++pass) {
                 proj_tn(Q, k, R, j0, P, W, red);
-                mark(pb + 1 + 2 * pass);
+                if (!xsum(xs, W, j0 * NB)) { fail_barrier(); return; }
+                if (wg == 0) mark(pb + 1 + 2 * pass);
                 proj_update(Q, k, R, j0, P, W);
                 for (int e = threadIdx.x; e < j0 * NB; e += LSB_NT) racc[e] += W[e];
                 __syncthreads();
-                mark(pb + 2 + 2 * pass);
+                if (wg == 0) mark(pb + 2 + 2 * pass);
             }
         }
         // ---- inside the panel: CholeskyQR2 (column-scaled first stage), or
         // CGS2 column by column for an ill-conditioned panel
         int stages = 0;
         // traced runs: slots 160 + 8 b + 4 stage + (0 .. 3) for panel b < 12
-        unsigned long long* str = (a.trace && j0 / NB < 12) ? a.trace + 160 + 8 * (j0 / NB) : nullptr;
+        unsigned long long* str = (a.trace && wg == 0 && j0 / NB < 12) ? a.trace + 160 + 8 * (j0 / NB) : nullptr;
         while (stages < 2) {
             unsigned long long* t4 = str ? str + 4 * stages : nullptr;
-            if (!cholqr_stage(P, R, nb, stages == 0, G, Lm, sc, rcur, rtmp, red, &s_ok, t4)) break;
+            if (!cholqr_stage(P, R, nb, stages == 0, G, Lm, sc, rcur, rtmp, red, &s_ok, t4, xs)) break;
             ++stages;
         }
+        if (xs.failed) { fail_barrier(); return; }
         if (stages < 2) {
             // rtmp accumulates the CGS2 factor of the current P (upper, 16 x 16)
             if (threadIdx.x < 256) rtmp[threadIdx.x] = 0.0;
@@ -498,6 +572,7 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
                             }
                         }
                         block_multi_sum<16>(part, red, coef);
+                        if (!xsum(xs, coef, 16)) { fail_barrier(); return; }
                         for (int i = threadIdx.x; i < R; i += LSB_NT) {
                             double x = P[p * RP + i];
 #pragma unroll
@@ -516,7 +591,13 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
                     const double x = P[p * RP + i];
                     nn = fma(x, x, nn);
                 }
-                const double nrm = sqrt(block_sum1(nn, red));
+                double* nsum = coef;           // free here: one slot for the cross-workgroup sum
+                const double nloc = block_sum1(nn, red);
+                if (threadIdx.x == 0) nsum[0] = nloc;
+                __syncthreads();
+                if (!xsum(xs, nsum, 1)) { fail_barrier(); return; }
+                const double nrm = sqrt(nsum[0]);
+                __syncthreads();
                 if (nrm > 0.0 && isfinite(nrm))
                     for (int i = threadIdx.x; i < R; i += LSB_NT) P[p * RP + i] = P[p * RP + i] / nrm;
                 if (threadIdx.x == 0) rtmp[p * 16 + p] = nrm;
@@ -554,13 +635,15 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
             if (threadIdx.x == 0) { a.ctl->ls_status = -4; a.ctl->status = -4; }
             return;
         }
-        mark(pb + 5);
-        // ---- the panel's orthonormal columns join Q; its R columns (and d)
+        if (wg == 0) mark(pb + 5);
+        // ---- the panel's orthonormal columns join Q (this workgroup's rows);
+        // its R columns (and d), the same in every workgroup, are written by
+        // the first
         for (int e = threadIdx.x; e < R * NB; e += LSB_NT) {
             const int i = e / NB, p = e - i * NB;
             if (p < nb && j0 + p < kd) Q[(long long)i * k + j0 + p] = P[p * RP + i];
         }
-        for (int e = threadIdx.x; e < (j0 + nb) * nb; e += LSB_NT) {
+        for (int e = threadIdx.x; wg == 0 && e < (j0 + nb) * nb; e += LSB_NT) {
             const int c = e / nb, p = e - c * nb;
             const int col = j0 + p;
             if (c > col) continue;
@@ -569,8 +652,9 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        mark(pb + 6);
+        if (wg == 0) mark(pb + 6);
     }
+    if (wg != 0) return;       // the substitution and the history: the first workgroup
     // ---- residual history and back substitution R y = d (d and the
     // reciprocals of R's diagonal staged in LDS)
     double* dl = W;                                // kd, overwritten by the substitution
@@ -633,24 +717,39 @@ static size_t lsb_bytes(int rows, int k)
     return sizeof(double) * ((size_t)PNB * panel_ld(rows) + 2 * (size_t)(k + 1) * PNB + (size_t)LSB_NW * 256 + 4 * 256 + 32);
 }
 
-int small_ls_panel(int s, int k, double lam, size_t lds_max)
+// Workgroups of the row-split form: about LS_ROWS_PER_WG rows each (one
+// workgroup below 256 rows, where the barriers would cost more than the
+// rows), at most LS_MWG_MAX.
+#ifndef LS_ROWS_PER_WG
+#define LS_ROWS_PER_WG 100
+#endif
+int small_ls_wgs(int s, double lam)
 {
     const int rows = lam > 0.0 ? 2 * s : s;
-    if (lsb_bytes(rows, k) + 256 <= lds_max) return PNB;   // 256: static LDS of the kernel
+    if (rows < 256) return 1;
+    return std::max(1, std::min(LS_MWG_MAX, rows / LS_ROWS_PER_WG));
+}
+
+int small_ls_panel(int s, int k, double lam, int nwg, size_t lds_max)
+{
+    const int rows = lam > 0.0 ? 2 * s : s;
+    const int local = (rows + nwg - 1) / std::max(1, nwg);
+    if (lsb_bytes(local, k) + 256 <= lds_max) return PNB;  // 256: static LDS of the kernel
     return 0;
 }
 
 hipError_t launch_small_ls_blocked(int nb, const LsArgs& a, hipStream_t st)
 {
     const int rows = a.lam > 0.0 ? 2 * a.s : a.s;
-    const size_t lds = lsb_bytes(rows, a.k);
+    const int nwg = std::max(1, a.nwg);
+    const size_t lds = lsb_bytes((rows + nwg - 1) / nwg, a.k);
     if (nb != PNB) return hipErrorInvalidValue;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)small_ls_blocked_kernel<PNB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(small_ls_blocked_kernel<PNB>, dim3(std::max(1, a.nrhs)), dim3(LSB_NT), lds, st, a);
+    hipLaunchKernelGGL(small_ls_blocked_kernel<PNB>, dim3(nwg, std::max(1, a.nrhs)), dim3(LSB_NT), lds, st, a);
     return hipGetLastError();
 }
 

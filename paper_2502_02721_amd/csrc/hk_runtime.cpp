@@ -475,7 +475,7 @@ hk_params effective_params(const hk_params& p)
 
 struct WsLayout {
     size_t ctl, L, D, H, W, tp, gp, PD, PL, pvD, pvL, amv, ami, zpart, fpart, cpart, Z, F, c;
-    size_t Q, R, r, y, yp, res, d, trace, scale, wpart, sval, sidx, T, T1, call, part, total;
+    size_t Q, R, r, y, yp, res, d, xpart, trace, scale, wpart, sval, sidx, T, T1, call, part, total;
     size_t region;          // bytes of one right-hand side's region (regions first, side by side)
     int trace_cap;
     int64_t ldl, ldd;
@@ -519,6 +519,7 @@ WsLayout ws_layout(const hk_op* op, const hk_params* p, int rect, int G, int nsl
     w.yp = take(sizeof(double) * k);
     w.res = take(sizeof(double) * k);
     w.d = take(sizeof(double) * k);
+    w.xpart = take(sizeof(double) * 2 * (size_t)small_ls_wgs(s, p->lambda) * ls_xcap(k));
     w.trace_cap = (p->flags & HK_FLAG_TRACE) ? 2 * (6 * kp1 + 8) + 16 * (kp1 + 1) : 0;
     w.trace = take(sizeof(unsigned long long) * (size_t)std::max(1, w.trace_cap + (w.trace_cap ? ARR_SLOTS + LS_TRACE : 0)));
     w.scale = take(sizeof(double) * kp1);
@@ -1053,7 +1054,14 @@ static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rec
     c.n = (int)op->n; c.k = p->k; c.L = a.L; c.ldl = a.ldl; c.y = l.y; c.ctl = a.ctl;
     c.rhs_stride = (long long)w.region;
     c.scale = (pl.kernel == OP_BLUR_ONEBAR) ? a.scale : nullptr;
-    l.nb = small_ls_panel(p->s, p->k, p->lambda, op->ctx->lds_max);
+    // the row-split least-squares kernel spreads the rows of [Z; lambda F]
+    // over several workgroups; a capped grid (a share of the device, as in
+    // the serving loop) keeps one workgroup per right-hand side
+    l.xpart = (double*)(base + w.xpart);
+    l.timeout = a.timeout_ticks;
+    l.nwg = p->max_workgroups > 0 ? 1 : small_ls_wgs(p->s, p->lambda);
+    l.nb = small_ls_panel(p->s, p->k, p->lambda, l.nwg, op->ctx->lds_max);
+    if (l.nb == 0) l.nwg = 1;
     if (l.nb == 0 && (size_t)small_ls_lds_bytes(p->s, p->k, p->lambda) > op->ctx->lds_max)
         return fail(HK_EUNSUPPORTED, "sketch size too large for the least-squares kernel's LDS");
     return HK_OK;
