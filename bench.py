@@ -207,7 +207,7 @@ def serving(hk, ctx, n: int, rate: float, slots: int):
                    "1024 px deblurring exceeds the single-kernel tile plan and is left out"}
 
 
-def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int):
+def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int, only: bool = False):
     """Several right-hand sides on the 512 x 512 deblurring operator solved
     together (hk_params.nrhs): the workload's operator and settings with a
     Gaussian sketch of s = 400 (its block contraction covers all the bases),
@@ -218,7 +218,7 @@ def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int):
     import workloads as W
     P = W.config("c2").replace(sketch=W.SKETCH_GAUSSIAN)
     out = {}
-    for nr in sorted({1, nrhs}):
+    for nr in ([nrhs] if only else sorted({1, nrhs})):
         probs = W.blur_rhs_family(P, nr)
         op = hk.Operator.blur(ctx, P.ny, P.nx, P.taps_y, P.taps_x, P.radius, P.bc, hk.HK_F32)
         sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, basis_dtype=hk.HK_F32, nrhs=nr)
@@ -268,6 +268,8 @@ def main():
     ap.add_argument("--workload", default="c2", help=argparse.SUPPRESS)
     ap.add_argument("--no-csr", dest="csr", action="store_false", help="skip the CSR tomography line")
     ap.add_argument("--rhs", type=int, default=4, help="right-hand sides of the multi-right-hand-side line (0: skip)")
+    ap.add_argument("--rhs-only", action="store_true",
+                    help="run only the multi-right-hand-side line (--rhs right-hand sides, no single-solve line)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run only a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -282,6 +284,11 @@ def main():
     import workloads as W
     import paper_2502_02721_amd as hk
 
+    if args.rhs_only:
+        ctx = hk.Context(0)
+        print(json.dumps({"multi_rhs": multi_rhs(hk, ctx, max(1, args.rhs), args.steps, args.warmup, only=True)}),
+              flush=True)
+        return
     P = W.config(args.workload)
     tdt = np.float32 if P.dtype == "f32" else np.float64
     bdt = {"f64": hk.HK_F64, "f32": hk.HK_F32, "bf16": hk.HK_BF16, "f16": hk.HK_F16}[P.basis_dtype]

@@ -200,6 +200,10 @@ __device__ __forceinline__ Tile tile_info(const Space& sp, int t)
         ti.x0 = (t % sp.ntx) * sp.TX;
         ti.E = sp.TY * sp.TX;
         ti.start = 0;
+    } else if (sp.kind == 2) {
+        ti.start = sp.st[t];
+        ti.E = sp.st[t + 1] - ti.start;
+        ti.y0 = ti.x0 = 0;
     } else {
         ti.start = range_start(t, sp.len, sp.ntile);
         ti.E = range_start(t + 1, sp.len, sp.ntile) - ti.start;
@@ -227,6 +231,16 @@ __device__ __forceinline__ void owner_of(const Space& sp, int gi, int& t, int& e
         const int y = gi / sp.nx, x = gi % sp.nx;
         t = (y / sp.TY) * sp.ntx + x / sp.TX;
         e = (y % sp.TY) * sp.TX + (x % sp.TX);
+    } else if (sp.kind == 2) {
+        // the last tile whose start is <= gi (starts increase strictly)
+        int lo = 0, hi = sp.ntile - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sp.st[mid] <= gi) lo = mid;
+            else hi = mid - 1;
+        }
+        t = lo;
+        e = gi - sp.st[lo];
     } else {
         int c = (int)(((long long)gi * sp.ntile) / sp.len);
         while (c + 1 < sp.ntile && range_start(c + 1, sp.len, sp.ntile) <= gi) ++c;

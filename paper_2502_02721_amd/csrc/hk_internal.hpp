@@ -36,10 +36,11 @@ enum SketchKind { SK_GAUSS = 0, SK_SPARSE = 1 };
 // tile per workgroup.  kind 0: 2-D image tiles TY x TX (row-major image of
 // nx columns); kind 1: contiguous ranges [t*len/ntile, (t+1)*len/ntile).
 struct Space {
-    int kind;
+    int kind;                    // 0: 2-D image tiles; 1: equal row ranges; 2: row ranges at st[]
     int len;
     int ntile;
     int ny, nx, TY, TX, ntx;
+    const int* st;               // kind 2: tile t holds [st[t], st[t + 1]), st[ntile] = len (device)
 };
 
 // Device control block at the start of the workspace: status words, then

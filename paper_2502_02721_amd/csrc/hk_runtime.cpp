@@ -106,6 +106,14 @@ struct hk_op {
     int lpr = 16, lprt = 16;
     double anorm = 0.0;                // ||A||_inf (max absolute row sum)
     double anorm_t = 0.0;              // ||A^T||_inf
+    // row pointers of A and A^T on the host, for the tile ranges below
+    std::vector<int64_t> h_rp, h_rpt;
+    // tile ranges balanced by nonzeros, per grid size: d holds the starts of
+    // the m-space (G + 1 ints), then of the n-space; d == nullptr records a
+    // grid for which no balanced ranges fit the plan
+    struct CsrPart { int G = 0; int ept = 0; int* d = nullptr; };
+    std::vector<CsrPart> parts;
+    std::mutex part_mu;
 };
 
 struct hk_solve {
@@ -607,7 +615,77 @@ static void op_free(hk_op* op)
     hipFree(op->d_rpt);
     hipFree(op->d_cit);
     hipFree(op->d_cvt);
+    for (auto& pt : op->parts) hipFree(pt.d);
     delete op;
+}
+
+// Row ranges of G tiles of about equal weight nnz_i + alpha per row, alpha =
+// beta times the mean row length (at least 1), every tile non-empty: tile t
+// holds [st[t], st[t + 1]).  With C(i) = rp[i] + alpha i and the cut st[t] =
+// the first i with C(i) >= t W / G (W = C(len)), a tile [a, b) has
+// C(b - 1) - C(a) < W / G, so fewer than (nnz / alpha + len) / G + 1 rows
+// (about twice the mean for beta = 1); the clamps that keep every tile
+// non-empty can only matter for a few huge rows, and the caller checks the
+// largest tile against the plan.
+static bool balanced_ranges(const std::vector<int64_t>& rp, int G, double beta, std::vector<int>& st, int& maxrows)
+{
+    const int64_t len = (int64_t)rp.size() - 1;
+    if (G < 1 || len < G) return false;
+    const double alpha = std::max(1.0, beta * (double)rp[len] / (double)len);
+    const double W = (double)rp[len] + alpha * (double)len;
+    st.assign((size_t)G + 1, 0);
+    st[G] = (int)len;
+    int64_t lo = 0;
+    for (int t = 1; t < G; ++t) {
+        const double target = W * t / G;
+        // the smallest i in [lo + 1, len - (G - t)] with rp[i] + alpha i >= target
+        int64_t a = lo + 1, b = len - (G - t);
+        while (a < b) {
+            const int64_t mid = (a + b) / 2;
+            if ((double)rp[mid] + alpha * (double)mid >= target) b = mid;
+            else a = mid + 1;
+        }
+        st[t] = (int)a;
+        lo = a;
+    }
+    maxrows = 0;
+    for (int t = 0; t < G; ++t) maxrows = std::max(maxrows, st[t + 1] - st[t]);
+    return true;
+}
+
+// Balanced tile ranges of a CSR operator for a plan of G tiles of at most
+// NT * ept rows, cached on the operator.  Computed, and their device copy
+// allocated, only when may_alloc; nullptr when there are none (the plan then
+// keeps equal row ranges).
+static const int* csr_partition(hk_op* op, int G, int ept, int rect, bool may_alloc)
+{
+    std::lock_guard<std::mutex> lk(op->part_mu);
+    for (const auto& pt : op->parts)
+        if (pt.G == G && pt.ept == ept) return pt.d;
+    if (!may_alloc) return nullptr;
+    hk_op::CsrPart cp;
+    cp.G = G;
+    cp.ept = ept;
+    const int cap = NT * ept;
+    std::vector<int> sm, sn;
+    for (double beta : {1.0, 2.0, 4.0}) {
+        int mm = 0, mn = 0;
+        if (!balanced_ranges(op->h_rp, G, beta, sm, mm)) break;
+        if (rect && !balanced_ranges(op->h_rpt, G, beta, sn, mn)) break;
+        if (mm > cap || (rect && mn > cap)) continue;
+        if (!rect) sn = sm;
+        int* d = nullptr;
+        if (hipMalloc(&d, sizeof(int) * 2 * ((size_t)G + 1)) != hipSuccess) break;
+        if (hipMemcpy(d, sm.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d + G + 1, sn.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice) != hipSuccess) {
+            hipFree(d);
+            break;
+        }
+        cp.d = d;
+        break;
+    }
+    op->parts.push_back(cp);
+    return cp.d;
 }
 
 hk_status hk_op_create_blur(hk_context* ctx, int64_t ny, int64_t nx, const double* taps_y,
@@ -785,6 +863,8 @@ hk_status hk_op_create_csr(hk_context* ctx, int64_t m, int64_t n, int64_t nnz, c
     op->anorm = anorm; op->anorm_t = anorm_t;
     op->lpr = lanes_per_row((double)nnz / (double)m);
     op->lprt = lanes_per_row((double)nnz / (double)n);
+    op->h_rp.assign(rowptr, rowptr + m + 1);
+    op->h_rpt = rpt;
     const size_t nb = std::max<int64_t>(nnz, 1);
     bool ok = hipMalloc(&op->d_rp, sizeof(int64_t) * (m + 1)) == hipSuccess &&
               hipMalloc(&op->d_ci, sizeof(int32_t) * nb) == hipSuccess &&
@@ -922,7 +1002,7 @@ static hk_status solve_plan(hk_op* op, const hk_params* p_in, hk_params* pe, int
 
 // Fill a solve's arguments for the workspace at `base` (laid out as `w`).
 static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rect, const Plan& pl,
-                            const WsLayout& w, unsigned char* base, hipStream_t stream)
+                            const WsLayout& w, unsigned char* base, hipStream_t stream, bool may_alloc)
 {
     sv->op = op;
     sv->prm = *p;
@@ -956,6 +1036,16 @@ static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rec
     a.xcd_map = (pl.G % 8 == 0) ? 1 : 0;
     a.spm = pl.spm;
     a.spn = pl.spn;
+    if (pl.kernel == OP_CSR) {
+        // CSR tiles balanced by nonzeros (plus a row term for the bases),
+        // when the operator has (or may compute) ranges that fit the plan
+        if (const int* st = csr_partition(op, pl.G, pl.ept, rect, may_alloc)) {
+            a.spm.kind = 2;
+            a.spm.st = st;
+            a.spn.kind = 2;
+            a.spn.st = rect ? st + pl.G + 1 : st;
+        }
+    }
     a.ny = op->ny; a.nx = op->nx; a.r = op->r; a.bc = op->bc;
     a.taps_y = op->d_taps;
     a.taps_x = op->d_taps ? op->d_taps + 2 * op->r + 1 : nullptr;
@@ -1107,7 +1197,7 @@ static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t
         hk_solve_destroy(sv);
         return fail(HK_EDEVICE, "zeroing the workspace failed");
     }
-    st = solve_bind(sv, op, p, rect, pl, w, (unsigned char*)sv->ws, stream);
+    st = solve_bind(sv, op, p, rect, pl, w, (unsigned char*)sv->ws, stream, true);
     if (st) {
         hk_solve_destroy(sv);
         return st;
@@ -1218,7 +1308,7 @@ hk_status hk_solve_run_noalloc(hk_op* op, const hk_params* p_in, const void* b_d
     }
     const WsLayout w = ws_layout(op, &pe, rect, pl.G, pl.nslot);
     hk_solve sv;                       // launch arguments only: no events, no workspace of its own
-    st = solve_bind(&sv, op, &pe, rect, pl, w, base, ctx->stream);
+    st = solve_bind(&sv, op, &pe, rect, pl, w, base, ctx->stream, false);
     if (st) return st;
     // the previous call's contents: clear everything before the bases (each
     // basis column is written before it is read)
