@@ -32,11 +32,16 @@ CSRC = os.path.join(ROOT, "paper_2502_02721_amd", "csrc")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "blur_iterate_kernel_deblur512_pmc.md")
 
 
+# the sources that define, plan and launch the basis kernel of the bench line
+KERNEL_SOURCES = ("hk_blur.hpp", "hk_device.hpp", "hk_internal.hpp", "hk_iter_f32.hip", "hk_kernels.hip",
+                  "hk_runtime.cpp")
+
+
 def csrc_digest() -> str:
-    """SHA-256 over the kernel sources (names and contents, sorted)."""
+    """SHA-256 over the basis kernel's sources (names and contents, in order)."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
+    for name in KERNEL_SOURCES:
         h.update(name.encode())
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
@@ -207,16 +212,19 @@ def serving(hk, ctx, n: int, rate: float, slots: int):
                    "1024 px deblurring exceeds the single-kernel tile plan and is left out"}
 
 
-def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int, only: bool = False):
+def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int, only: bool = False, sparse: bool = False):
     """Several right-hand sides on the 512 x 512 deblurring operator solved
-    together (hk_params.nrhs): the workload's operator and settings with a
-    Gaussian sketch of s = 400 (its block contraction covers all the bases),
-    right-hand sides from workloads.blur_rhs_family.  Reports Hessenberg
-    iterations per second summed over the right-hand sides and the basis
-    kernel's algorithmic bandwidth (nrhs times one solve's bytes)."""
+    together (hk_params.nrhs): the workload's operator and settings, with
+    its own sparse-sign sketch (sparse) or a Gaussian sketch of s = 400
+    (whose block contraction covers all the bases); right-hand sides from
+    workloads.blur_rhs_family.  Reports Hessenberg iterations per second
+    summed over the right-hand sides and the basis kernel's algorithmic
+    bandwidth (nrhs times one solve's bytes)."""
     import torch
     import workloads as W
-    P = W.config("c2").replace(sketch=W.SKETCH_GAUSSIAN)
+    P = W.config("c2")
+    if not sparse:
+        P = P.replace(sketch=W.SKETCH_GAUSSIAN)
     out = {}
     for nr in ([nrhs] if only else sorted({1, nrhs})):
         probs = W.blur_rhs_family(P, nr)
@@ -251,7 +259,8 @@ def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int, only: bool = False):
         sv.close()
         op.close()
         print(f"# multi-rhs {nr}: {out[str(nr)]['ms_per_solve']} ms per solve", file=sys.stderr, flush=True)
-    return {"workload": "deblur-512x512 operator, k=100, Gaussian s=400, lambda=1e-2, FP32 bases; "
+    sk = "sparse-sign s=400 zeta=8" if sparse else "Gaussian s=400"
+    return {"workload": f"deblur-512x512 operator, k=100, {sk}, lambda=1e-2, FP32 bases; "
                         f"{nrhs} right-hand sides solved together vs one",
             "runs": out}
 
@@ -360,6 +369,8 @@ def main():
         out["csr_tomography"] = csr_line(hk, ctx, 5, 2)
     if args.rhs > 0:
         out["multi_rhs"] = multi_rhs(hk, ctx, args.rhs, max(3, args.steps // 2), 2)
+        # the workload's own sketch: three right-hand sides fit its LDS plan
+        out["multi_rhs_sparse"] = multi_rhs(hk, ctx, 3, max(3, args.steps // 2), 2, sparse=True)
     if args.serve_requests > 0:
         out["serving"] = serving(hk, ctx, args.serve_requests, args.serve_rate, args.serve_slots)
     if not args.no_cpu_baseline:
