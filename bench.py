@@ -194,6 +194,22 @@ def serving(hk, ctx, n: int, rate: float, slots: int):
         time.sleep(2e-5)
     res = [srv.result(t) for t in tickets]
     srv.close()
+    # the mix's results: the first request of every (kind, size) bucket,
+    # solved alone with the grid it had in the mix, gives the same x bit for bit
+    checked, differ, seen = 0, 0, set()
+    for q, r in zip(reqs, res):
+        key = (q["kind"], q["N"])
+        if key in seen or r["status"] < 0:
+            continue
+        seen.add(key)
+        i = q["id"]
+        sv = hk.Solve(ops[i], q["k"], q["s"], q["lam"], q["sketch"], q["zeta"], q["seed"],
+                      max_workgroups=r["workgroups"])
+        xa = sv.run(bs[i])
+        sv.wait()
+        checked += 1
+        differ += 0 if torch.equal(xa, xs[i]) else 1
+        sv.close()
     bad = [r["status"] for r in res if r["status"] < 0]
     lat = np.array([r["t_finish"] - r["t_submit"] for r in res]) * 1e3
     span = max(r["t_finish"] for r in res) - min(r["t_submit"] for r in res)
@@ -207,6 +223,8 @@ def serving(hk, ctx, n: int, rate: float, slots: int):
                            "p99": round(float(np.percentile(lat, 99)), 3),
                            "mean": round(float(lat.mean()), 3)},
             "max_concurrent": int(conc), "errors": len(bad),
+            "checked_against_alone": {"requests": checked, "differ": differ,
+                                      "rule": "first request of each (kind, size) bucket, same grid, x bit for bit"},
             "mix": "deblur 128-512 px (sigma 1-6, zero/reflective, sparse sign), tomography 64-256 px "
                    "(60-180 angles, Gaussian), k 20-200, s = 2(k+1), lambda in {0, 1e-3, 1e-2}, FP32; "
                    "1024 px deblurring exceeds the single-kernel tile plan and is left out"}

@@ -313,6 +313,16 @@ hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev);
  * x_dev is written.  Errors: HK_EINVAL for kp outside [1, k_done]. */
 hk_status hk_solve_get_prefix_solution(hk_solve* sv, int32_t kp, void* x_dev);
 
+/* True residual norms of the selected right-hand side: res[kp-1] =
+ * ||b - A x_kp||_2 for kp = 1 .. k_done (x_kp as hk_solve_get_prefix_solution;
+ * the quantity the paper's sketched residual stands in for, Sec. 2),
+ * entries past k_done are 0.  res: host array of k doubles.  Optional and
+ * not free: one prefix solution, one product with A and one FP64 norm per
+ * kp, on the context stream, in device buffers allocated for the call.
+ * b is read from the array the last hk_solve_run was given, which must
+ * still hold that right-hand side.  Errors: HK_EINVAL before any run. */
+hk_status hk_solve_get_true_residuals(hk_solve* sv, double* res);
+
 /* Workgroups of the solve's basis kernel (its grid; one per tile). */
 hk_status hk_solve_grid(const hk_solve* sv, int32_t* workgroups);
 

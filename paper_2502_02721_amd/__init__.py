@@ -40,7 +40,7 @@ ABI_FUNCTIONS = (
     "hk_solve_run", "hk_solve_run_noalloc", "hk_solve_wait", "hk_solve_info", "hk_solve_select_rhs",
     "hk_solve_get_hessenberg",
     "hk_solve_get_pivots", "hk_solve_get_residuals", "hk_solve_get_sketches",
-    "hk_solve_get_basis", "hk_solve_get_prefix_solution", "hk_solve_timing", "hk_solve_grid", "hk_solve_timing_history", "hk_solve_get_trace",
+    "hk_solve_get_basis", "hk_solve_get_prefix_solution", "hk_solve_get_true_residuals", "hk_solve_timing", "hk_solve_grid", "hk_solve_timing_history", "hk_solve_get_trace",
     "hk_solve_destroy", "hk_server_create", "hk_server_destroy", "hk_server_submit", "hk_server_poll",
     "hk_server_wait", "hk_server_result",
 )
@@ -97,6 +97,7 @@ def lib():
             "hk_solve_get_sketches": ([vp, vp, vp, vp], st),
             "hk_solve_get_basis": ([vp, i32, vp], st),
             "hk_solve_get_prefix_solution": ([vp, i32, vp], st),
+            "hk_solve_get_true_residuals": ([vp, vp], st),
             "hk_solve_timing": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double)], st),
             "hk_solve_grid": ([vp, C.POINTER(C.c_int32)], st),
             "hk_solve_timing_history": ([vp, i32, vp, vp, C.POINTER(i32)], st),
@@ -503,6 +504,12 @@ class Solve(_Owner):
         self.op._vec(out, self.op.n, "x")
         _check(lib().hk_solve_get_prefix_solution(C.c_void_p(self.handle), kp, C.c_void_p(out.data_ptr())))
         return out
+
+    def true_residuals(self):
+        """||b - A x_kp|| for kp = 1 .. k (0 past k_done), from the last run's b."""
+        res = np.zeros(self.k, dtype=np.float64)
+        _check(lib().hk_solve_get_true_residuals(C.c_void_p(self.handle), res.ctypes.data_as(C.c_void_p)))
+        return res
 
     def timing(self):
         return hk_solve_timing(self.handle)

@@ -355,6 +355,36 @@ hipError_t launch_prefix_y(const double* R, const double* d, int k, int kp, int 
     return hipGetLastError();
 }
 
+// out = ||b - y||_2 over m entries of the operator's type, accumulated in
+// FP64: each thread sums a fixed stride of entries, then a fixed tree over
+// the workgroup (one workgroup, so the order never changes).
+template <typename T>
+__global__ __launch_bounds__(1024) void resid_norm_kernel(const T* b, const T* y, long long m, double* out)
+{
+    __shared__ double red[1024];
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < m; i += 1024) {
+        const double d = (double)b[i] - (double)y[i];
+        acc = fma(d, d, acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+hipError_t launch_resid_norm(int dtype, const void* b, const void* y, long long m, double* out, hipStream_t st)
+{
+    if (dtype == 0) hipLaunchKernelGGL(resid_norm_kernel<double>, dim3(1), dim3(1024), 0, st, (const double*)b,
+                                       (const double*)y, m, out);
+    else hipLaunchKernelGGL(resid_norm_kernel<float>, dim3(1), dim3(1024), 0, st, (const float*)b,
+                            (const float*)y, m, out);
+    return hipGetLastError();
+}
+
 // dst[j * len + i] = scale[j] * src[j * ld + i] (normalised copy of a basis)
 template <typename TB>
 __global__ __launch_bounds__(256) void scale_basis_kernel(const TB* src, int64_t ld, const double* scale,

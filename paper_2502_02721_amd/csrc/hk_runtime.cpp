@@ -143,6 +143,7 @@ struct hk_solve {
     int sel = 0;                           // the one the getters report
     double* call = nullptr;                // S2 b of the first right-hand side (the others follow)
     double* yp = nullptr;                  // prefix-solution coefficients (first right-hand side's region)
+    const void* b_last = nullptr;          // right-hand side(s) of the last run (for the true residuals)
     size_t region = 0;                     // bytes between right-hand sides' regions
     double* T = nullptr;
     double* T1 = nullptr;
@@ -565,6 +566,8 @@ hk_status current_device(hk_context* ctx)
 
 }  // namespace
 
+static hk_status op_apply_on(hk_op* op, int transpose, const void* x_dev, void* y_dev, hipStream_t st);
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -899,6 +902,14 @@ hk_status hk_op_apply(hk_op* op, int32_t transpose, const void* x_dev, void* y_d
     if (transpose && op->kind != OP_CSR) return fail(HK_EUNSUPPORTED, "A^T products are provided for CSR operators");
     hk_status st = current_device(op->ctx);
     if (st) return st;
+    return op_apply_on(op, transpose, x_dev, y_dev, op->ctx->stream);
+}
+
+}  // extern "C"
+
+// y = A x (or A^T x) on stream st, in the operator's own product kernel.
+static hk_status op_apply_on(hk_op* op, int transpose, const void* x_dev, void* y_dev, hipStream_t st)
+{
     ApplyArgs a{};
     a.transpose = transpose;
     a.x = x_dev;
@@ -939,9 +950,11 @@ hk_status hk_op_apply(hk_op* op, int32_t transpose, const void* x_dev, void* y_d
         a.lds_w = 0;
         a.lds_total = (int)(sizeof(double) * per);
     }
-    HIP_TRY(launch_apply(op->dtype, op->kind, ept, a, op->ctx->stream));
+    HIP_TRY(launch_apply(op->dtype, op->kind, ept, a, st));
     return HK_OK;
 }
+
+extern "C" {
 
 hk_status hk_op_destroy(hk_op* op)
 {
@@ -1276,6 +1289,7 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
     sv->ev2 = sv->ev[slot][2];
     st = solve_enqueue(sv, b_dev, x_dev, sv->stream, sv->ev0, sv->ev1, sv->ev2);
     if (st) return st;
+    sv->b_last = b_dev;
     sv->runs++;
     sv->ran = true;
     sv->waited = false;
@@ -1456,6 +1470,60 @@ hk_status hk_solve_get_prefix_solution(hk_solve* sv, int32_t kp, void* x_dev)
     c.kcap = kp;
     HIP_TRY(launch_combine(sv->tb, sv->op->dtype, c, 1, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return HK_OK;
+}
+
+hk_status hk_solve_get_true_residuals(hk_solve* sv, double* res)
+{
+    hk_status st = ensure_done(sv);
+    if (st) return st;
+    if (!res) return fail(HK_EINVAL, "null output");
+    if (!sv->b_last) return fail(HK_EINVAL, "no run of this solve with a right-hand side to compare against");
+    hk_op* op = sv->op;
+    HIP_TRY(hipSetDevice(op->ctx->device));
+    const hipStream_t s = op->ctx->stream;
+    const int kd = sv->k_done, k = sv->prm.k;
+    const size_t es = dsize(op->dtype);
+    void* xt = nullptr;
+    void* ax = nullptr;
+    double* dres = nullptr;
+    auto cleanup = [&]() { hipFree(xt); hipFree(ax); hipFree(dres); };
+    if (hipMalloc(&xt, es * (size_t)op->n) != hipSuccess || hipMalloc(&ax, es * (size_t)op->m) != hipSuccess ||
+        hipMalloc(&dres, sizeof(double) * (size_t)std::max(1, k)) != hipSuccess) {
+        cleanup();
+        return fail(HK_ENOMEM, "hipMalloc of the residual buffers failed");
+    }
+    const size_t ro = (size_t)sv->sel * sv->region;
+    auto at = [&](auto* q) { return (decltype(q))((char*)q + ro); };
+    const void* b = (const char*)sv->b_last + (size_t)sv->sel * (size_t)op->m * es;
+    CombineArgs c = sv->ca;
+    c.L = (const char*)c.L + (size_t)sv->sel * (sv->prm.k + 1) * c.ldl * dsize(sv->prm.basis_dtype);
+    c.ctl = at(c.ctl);
+    c.y = at(sv->yp);
+    c.scale = c.scale ? at(c.scale) : nullptr;
+    c.x = xt;
+    hk_status out = HK_OK;
+    for (int kp = 1; kp <= kd && out == HK_OK; ++kp) {
+        // x_kp = L_kp y_kp, then ||b - A x_kp|| with the operator's own product
+        hipError_t e = launch_prefix_y(at(sv->la.R), at(sv->la.d), k, kp, sv->la.nb > 0 ? 1 : 0, at(sv->yp), s);
+        if (e == hipSuccess) {
+            c.kcap = kp;
+            e = launch_combine(sv->tb, op->dtype, c, 1, s);
+        }
+        if (e != hipSuccess) { out = fail(HK_EDEVICE, "%s", hipGetErrorString(e)); break; }
+        out = op_apply_on(op, 0, xt, ax, s);
+        if (out == HK_OK) {
+            e = launch_resid_norm(op->dtype == HK_F64 ? 0 : 1, b, ax, (long long)op->m, dres + (kp - 1), s);
+            if (e != hipSuccess) out = fail(HK_EDEVICE, "%s", hipGetErrorString(e));
+        }
+    }
+    if (out == HK_OK && kd > 0 &&
+        (hipMemcpyAsync(res, dres, sizeof(double) * kd, hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess))
+        out = fail(HK_EDEVICE, "copying the residuals failed");
+    cleanup();
+    if (out != HK_OK) return out;
+    for (int i = kd; i < k; ++i) res[i] = 0.0;
     return HK_OK;
 }
 

@@ -46,6 +46,8 @@ def test_version_and_null_argument_errors(hk):
     assert L.hk_op_create_blur(None, 4, 4, None, None, 1, 0, 0, None) == hk.HK_EINVAL
     assert L.hk_solve_create(None, None, None) == hk.HK_EINVAL
     assert L.hk_solve_create_with_workspace(None, None, None, 0, None) == hk.HK_EINVAL
+    assert L.hk_solve_get_true_residuals(None, None) == hk.HK_EINVAL
+    assert L.hk_solve_get_prefix_solution(None, 1, None) == hk.HK_EINVAL
     assert L.hk_solve_grid(None, None) == hk.HK_EINVAL
     assert L.hk_solve_select_rhs(None, 0) == hk.HK_EINVAL
     assert L.hk_solve_run_noalloc(None, None, None, None, None) == hk.HK_EINVAL

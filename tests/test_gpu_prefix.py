@@ -92,3 +92,48 @@ def test_prefix_of_selected_rhs_equals_single(hk, ctx):
         assert multi["k_done"] == single["k_done"]
         for kp in kps(single["k_done"]):
             np.testing.assert_array_equal(multi[kp], single[kp])
+
+
+def _host_apply(P, x):
+    """A x in FP64 on the host (scipy), on the operator as the GPU sees it."""
+    import scipy.sparse as sp
+    if P.kind == "blur":
+        return W.blur_apply_scipy(x.reshape(P.ny, P.nx), P.taps_y, P.taps_x, P.bc, psf=P.psf).ravel()
+    val = P.val.astype(storage_np(P.dtype)).astype(np.float64)
+    return sp.csr_matrix((val, P.col, P.rowptr), shape=(P.m, P.n)) @ x
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_true_residuals(hk, ctx, orc, name):
+    """||b - A x_kp|| from the library against the same norm of its own prefix
+    solutions evaluated on the host in FP64, and against the oracle's prefix
+    solutions (the definition: Sec. 2, the residual the sketch stands in for)."""
+    import torch
+    P = CASES[name]()
+    print(f"case {name}: m={P.m} n={P.n} k={P.k}", flush=True)
+    op = make_operator(hk, ctx, P)
+    bdt = hk.HK_F64 if P.basis_dtype == "f64" else hk.HK_F32
+    sv = hk.Solve(op, P.k, P.s, P.lam, P.sketch, P.zeta, P.seed, basis_dtype=bdt)
+    try:
+        b = torch.tensor(P.b.astype(storage_np(P.dtype)), device="cuda:0")
+        sv.run(b)
+        assert sv.wait() == 0
+        kd = sv.k_done()
+        tr = sv.true_residuals()
+        assert np.all(tr[kd:] == 0.0) and np.all(tr[:kd] > 0.0)
+        bh = P.b.astype(storage_np(P.dtype)).astype(np.float64)
+        own = np.array([np.linalg.norm(bh - _host_apply(P, sv.prefix_solution(kp).cpu().numpy().astype(np.float64)))
+                        for kp in range(1, kd + 1)])
+    finally:
+        sv.close()
+        op.close()
+    e_own = np.max(np.abs(tr[:kd] - own) / own)
+    o = orc.solve(rounded_problem(P), keep_basis=True)
+    ref = np.array([np.linalg.norm(bh - _host_apply(P, orc.prefix_solution(o, kp, P.lam))) for kp in range(1, kd + 1)])
+    e_or = np.max(np.abs(tr[:kd] - ref) / ref)
+    print(f"  true residuals: vs host norm of own prefixes {e_own:.2e}, vs oracle {e_or:.2e} "
+          f"(first {tr[0]:.4e}, last {tr[kd - 1]:.4e})", flush=True)
+    # FP64 operators: products and norms in FP64; FP32 operators: A x is
+    # rounded to FP32 by the product kernel
+    assert e_own <= (1e-12 if P.dtype == "f64" else 1e-5), e_own
+    assert e_or <= (1e-8 if P.dtype == "f64" else 1e-3), e_or
