@@ -259,7 +259,11 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev);
  * The array keeps the previous call's contents; each call clears what must
  * start at zero.  Calls that overlap on one device (other streams, other
  * threads) share the array and race: the caller orders them.  Asynchronous:
- * returns once the work is queued. */
+ * returns once the work is queued.  CSR operators: the row ranges balanced
+ * by nonzeros are computed (and allocated) when a solve is created; this
+ * call uses them only if a solve with the same grid was created on the
+ * operator before, and equal row ranges otherwise, in which case x equals
+ * the allocating path's to rounding rather than bit for bit. */
 #define HK_NOALLOC_MAX_BYTES (128u << 20)
 hk_status hk_solve_run_noalloc(hk_op* op, const hk_params* params, const void* b_dev, void* x_dev,
                                int32_t* info_dev);
