@@ -232,7 +232,7 @@ hipError_t launch_small_ls(const LsArgs& a, hipStream_t st);
 hipError_t launch_combine(int tb, int to, const CombineArgs& a, int nrhs, hipStream_t st);
 // y' = R(1:kp, 1:kp)^{-1} d(1:kp) (R column-major with leading dimension k),
 // by the same column-oriented substitution as the least-squares kernels
-// (recip: multiply by the reciprocal of the diagonal, as the blocked kernel)
+// (recip: multiply by the reciprocal of the diagonal, as the least-squares kernels do)
 // out = ||b - y||_2 (m entries of type dtype: 0 FP64, 1 FP32), FP64 sums in a fixed order
 hipError_t launch_resid_norm(int dtype, const void* b, const void* y, long long m, double* out, hipStream_t st);
 hipError_t launch_prefix_y(const double* R, const double* d, int k, int kp, int recip, double* yp,

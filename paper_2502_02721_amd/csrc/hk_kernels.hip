@@ -101,7 +101,7 @@ __global__ __launch_bounds__(LS_NT) void small_ls_kernel(LsArgs a_in)
     __syncthreads();
     if (threadIdx.x < 64) {
         for (int i = kd - 1; i >= 0; --i) {
-            const double yi = coef[i] / R[(long long)i * a.k + i];
+            const double yi = coef[i] * (1.0 / R[(long long)i * a.k + i]);
             __builtin_amdgcn_wave_barrier();
             if (lane == 0) a.y[i] = yi;
             for (int q = lane; q < i; q += 64) coef[q] = fma(-R[(long long)i * a.k + q], yi, coef[q]);

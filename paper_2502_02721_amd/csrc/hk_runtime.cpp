@@ -1460,7 +1460,7 @@ hk_status hk_solve_get_prefix_solution(hk_solve* sv, int32_t kp, void* x_dev)
     const size_t ro = (size_t)sv->sel * sv->region;
     auto at = [&](auto* q) { return (decltype(q))((char*)q + ro); };
     double* yp = at(sv->yp);
-    HIP_TRY(launch_prefix_y(at(sv->la.R), at(sv->la.d), sv->prm.k, kp, sv->la.nb > 0 ? 1 : 0, yp, s));
+    HIP_TRY(launch_prefix_y(at(sv->la.R), at(sv->la.d), sv->prm.k, kp, 1, yp, s));
     CombineArgs c = sv->ca;
     c.L = (const char*)c.L + (size_t)sv->sel * (sv->prm.k + 1) * c.ldl * dsize(sv->prm.basis_dtype);
     c.ctl = at(c.ctl);
@@ -1505,7 +1505,7 @@ hk_status hk_solve_get_true_residuals(hk_solve* sv, double* res)
     hk_status out = HK_OK;
     for (int kp = 1; kp <= kd && out == HK_OK; ++kp) {
         // x_kp = L_kp y_kp, then ||b - A x_kp|| with the operator's own product
-        hipError_t e = launch_prefix_y(at(sv->la.R), at(sv->la.d), k, kp, sv->la.nb > 0 ? 1 : 0, at(sv->yp), s);
+        hipError_t e = launch_prefix_y(at(sv->la.R), at(sv->la.d), k, kp, 1, at(sv->yp), s);
         if (e == hipSuccess) {
             c.kcap = kp;
             e = launch_combine(sv->tb, op->dtype, c, 1, s);
