@@ -208,6 +208,38 @@ def test_lslu_sampled_pivots_random_csr(hk, ctx, orc, dtype, sketch, lam):
     _parity(hk, ctx, orc, P.replace(pivot_sample=25))
 
 
+def long_row_csr(m, n, step, k, s, dtype, seed=17):
+    """CSR with row i holding (i * step) % n entries (empty rows included;
+    most rows longer than the 512 entries a wave loads in one batch), at
+    random sorted columns, values in [0.1, 1)."""
+    rng = np.random.default_rng(seed)
+    lens = (np.arange(m) * step) % n
+    rowptr = np.zeros(m + 1, np.int64)
+    rowptr[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, L, replace=False)) for L in lens]).astype(np.int32)
+    val = rng.uniform(0.1, 1.0, int(rowptr[-1]))
+    import scipy.sparse as sp
+    A = sp.csr_matrix((val, col, rowptr), shape=(m, n))
+    b = A @ rng.uniform(0, 1, n) + 0.01 * rng.standard_normal(m)
+    return W.Problem(name=f"longrows{m}x{n}", kind="csr", m=m, n=n, b=b, x_true=np.zeros(n), k=k, s=s,
+                     lam=0.0, sketch=W.SKETCH_GAUSSIAN, zeta=4, seed=W.SKETCH_SEED_BASE + 13, dtype=dtype,
+                     rowptr=rowptr, col=col, val=val.astype(storage_np(dtype)))
+
+
+@pytest.mark.parametrize("shape", ["square", "rect"])
+def test_csr_rows_longer_than_one_batch(hk, ctx, orc, shape):
+    # rows of 0 to about 1400 entries: a wave takes rows of more than 512
+    # entries in several batches, and empty rows as a whole
+    if shape == "square":
+        P = long_row_csr(1200, 1200, 37, k=20, s=42, dtype="f64")
+        assert np.diff(P.rowptr).max() > 1024 and (np.diff(P.rowptr) == 0).any()
+        _parity(hk, ctx, orc, P, method=hk.HK_METHOD_HESSENBERG)
+    else:
+        P = long_row_csr(700, 1500, 53, k=20, s=42, dtype="f64")
+        assert np.diff(P.rowptr).max() > 1024
+        _parity(hk, ctx, orc, P)
+
+
 def test_cmrh_sampled_pivots_square_csr(hk, ctx, orc):
     P = random_csr(500, 500, 0.03, k=30, s=62, dtype="f64").replace(pivot_sample=5)
     _parity(hk, ctx, orc, P, method=hk.HK_METHOD_HESSENBERG)
