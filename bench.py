@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import subprocess
 import os
 import sys
 import time
@@ -230,6 +231,22 @@ def serving(hk, ctx, n: int, rate: float, slots: int):
                    "1024 px deblurring exceeds the single-kernel tile plan and is left out"}
 
 
+def serving_child(args):
+    """The serving mix in a child process whose HIP runtime uses
+    args.serve_hw_queues hardware queues (read once, when HIP starts): with
+    HIP's default of 4, the server's slot streams share few queues and
+    their solves serialise.  Progress lines go to this process's stderr."""
+    env = dict(os.environ)
+    env["GPU_MAX_HW_QUEUES"] = str(args.serve_hw_queues)
+    cmd = [sys.executable, os.path.abspath(__file__), "--serving-only",
+           "--serve-requests", str(args.serve_requests), "--serve-rate", str(args.serve_rate),
+           "--serve-slots", str(args.serve_slots), "--serve-hw-queues", str(args.serve_hw_queues)]
+    r = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"serving run failed with exit status {r.returncode}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def multi_rhs(hk, ctx, nrhs: int, steps: int, warmup: int, only: bool = False, sparse: bool = False):
     """Several right-hand sides on the 512 x 512 deblurring operator solved
     together (hk_params.nrhs): the workload's operator and settings, with
@@ -291,7 +308,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512, help="serving mix size (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-hw-queues", type=int, default=12,
+                    help="hardware queues (GPU_MAX_HW_QUEUES) of the process that runs the serving mix; "
+                         "it runs in a child process when this differs from the current setting (0: this process)")
+    ap.add_argument("--serving-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--workload", default="c2", help=argparse.SUPPRESS)
     ap.add_argument("--no-csr", dest="csr", action="store_false", help="skip the CSR tomography line")
     ap.add_argument("--rhs", type=int, default=4, help="right-hand sides of the multi-right-hand-side line (0: skip)")
@@ -311,6 +332,12 @@ def main():
     import workloads as W
     import paper_2502_02721_amd as hk
 
+    if args.serving_only:
+        ctx = hk.Context(0)
+        res = serving(hk, ctx, args.serve_requests, args.serve_rate, args.serve_slots)
+        res["hw_queues"] = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+        print(json.dumps(res), flush=True)
+        return
     if args.rhs_only:
         ctx = hk.Context(0)
         print(json.dumps({"multi_rhs": multi_rhs(hk, ctx, max(1, args.rhs), args.steps, args.warmup, only=True)}),
@@ -390,7 +417,11 @@ def main():
         # the workload's own sketch: three right-hand sides fit its LDS plan
         out["multi_rhs_sparse"] = multi_rhs(hk, ctx, 3, max(3, args.steps // 2), 2, sparse=True)
     if args.serve_requests > 0:
-        out["serving"] = serving(hk, ctx, args.serve_requests, args.serve_rate, args.serve_slots)
+        if args.serve_hw_queues > 0 and os.environ.get("GPU_MAX_HW_QUEUES") != str(args.serve_hw_queues):
+            out["serving"] = serving_child(args)
+        else:
+            out["serving"] = serving(hk, ctx, args.serve_requests, args.serve_rate, args.serve_slots)
+            out["serving"]["hw_queues"] = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)

@@ -368,7 +368,10 @@ hk_status hk_solve_destroy(hk_solve* sv);
  * finished; its result is written to x_dev.  A request's solve is ordered
  * after the work queued on the context's stream when it was submitted (an
  * event recorded there at submission), so b_dev and x_dev may still be in
- * production on that stream; work queued there later is not waited for. */
+ * production on that stream; work queued there later is not waited for.
+ * The slots' streams run side by side only as far as the HIP runtime gives
+ * them hardware queues: GPU_MAX_HW_QUEUES (4 by default, read when the
+ * process first uses HIP) should exceed the number of slots. */
 hk_status hk_server_create(hk_context* ctx, int32_t slots, size_t budget_bytes, int32_t workgroups,
                            hk_server** out);
 hk_status hk_server_destroy(hk_server* srv);   /* waits for the running solves */
