@@ -85,6 +85,13 @@ enum { HK_METHOD_AUTO = 0, HK_METHOD_HESSENBERG = 1, HK_METHOD_CHANGING_HESSENBE
 
 enum { HK_FLAG_TRACE = 1 };
 
+/* Opaque handles.  The caller destroys each one exactly once.  Every entry
+ * point refuses, with HK_EINVAL and before reading the handle's memory, a
+ * null handle, one this library did not create, or one already destroyed
+ * (a destroyed handle whose address a newer handle reuses is that newer
+ * handle).  Operators and solves hold their context, and solves their
+ * operator: destroy solves before their operator, operators before their
+ * context. */
 typedef struct hk_context hk_context;
 typedef struct hk_op hk_op;
 typedef struct hk_solve hk_solve;

@@ -12,6 +12,7 @@
 #include <deque>
 #include <mutex>
 #include <thread>
+#include <unordered_set>
 #include <cfloat>
 #include <cmath>
 #include <cstdarg>
@@ -36,6 +37,38 @@ hk_status fail(hk_status st, const char* fmt, ...)
     g_err = buf;
     return st;
 }
+
+// Live handles: every context, operator, solve and server from its creation
+// to its destruction.  Entry points refuse a handle that is not live (null,
+// never created here, or already destroyed) with HK_EINVAL before touching
+// its memory, so a second destroy is an error rather than a double free.
+// (A destroyed handle whose address a new handle reuses is live again.)
+std::mutex g_live_mu;
+std::unordered_set<const void*> g_live;
+
+void live_add(const void* h)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(h);
+}
+
+bool live_take(const void* h)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return h && g_live.erase(h) == 1;
+}
+
+bool live(const void* h)
+{
+    if (!h) return false;
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return g_live.count(h) != 0;
+}
+
+#define HK_LIVE(h)                                                                         \
+    do {                                                                                   \
+        if (!live(h)) return fail(HK_EINVAL, (h) ? "unknown or destroyed handle " #h : "null handle " #h); \
+    } while (0)
 
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
@@ -595,13 +628,14 @@ hk_status hk_context_create(int32_t device, void* stream, hk_context** out)
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
         c->wall_rate_khz = (unsigned long long)rate;
     scratch_setup(device);    // the no-alloc entry point's workspace on this device
+    live_add(c);
     *out = c;
     return HK_OK;
 }
 
 hk_status hk_context_destroy(hk_context* ctx)
 {
-    if (!ctx) return fail(HK_EINVAL, "null context");
+    if (!live_take(ctx)) return fail(HK_EINVAL, ctx ? "unknown or destroyed context" : "null context");
     delete ctx;
     return HK_OK;
 }
@@ -694,6 +728,7 @@ static const int* csr_partition(hk_op* op, int G, int ept, int rect, bool may_al
 hk_status hk_op_create_blur(hk_context* ctx, int64_t ny, int64_t nx, const double* taps_y,
                             const double* taps_x, int32_t radius, hk_bc bc, hk_dtype dt, hk_op** out)
 {
+    HK_LIVE(ctx);
     if (!out) return fail(HK_EINVAL, "null output handle");
     *out = nullptr;
     if (!ctx || !taps_y || !taps_x) return fail(HK_EINVAL, "null argument");
@@ -728,6 +763,7 @@ hk_status hk_op_create_blur(hk_context* ctx, int64_t ny, int64_t nx, const doubl
         op_free(op);
         return fail(HK_EDEVICE, "hipMemcpy failed");
     }
+    live_add(op);
     *out = op;
     return HK_OK;
 }
@@ -735,6 +771,7 @@ hk_status hk_op_create_blur(hk_context* ctx, int64_t ny, int64_t nx, const doubl
 hk_status hk_op_create_gaussian_blur(hk_context* ctx, int64_t ny, int64_t nx, double sigma,
                                      int32_t radius, hk_bc bc, hk_dtype dt, hk_op** out)
 {
+    HK_LIVE(ctx);
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(HK_EINVAL, "sigma must be positive");
     if (radius < 0 || radius > 64) return fail(HK_EINVAL, "radius %d outside [0, 64]", radius);
     std::vector<double> g(2 * (size_t)radius + 1);
@@ -750,6 +787,7 @@ hk_status hk_op_create_gaussian_blur(hk_context* ctx, int64_t ny, int64_t nx, do
 hk_status hk_op_create_blur_psf(hk_context* ctx, int64_t ny, int64_t nx, const double* psf, int32_t radius,
                                 hk_bc bc, hk_dtype dt, hk_op** out)
 {
+    HK_LIVE(ctx);
     if (!out) return fail(HK_EINVAL, "null output handle");
     *out = nullptr;
     if (!ctx || !psf) return fail(HK_EINVAL, "null argument");
@@ -805,10 +843,11 @@ hk_status hk_op_create_blur_psf(hk_context* ctx, int64_t ny, int64_t nx, const d
     op->anorm = op->anorm_t = asum;
     bool ok = hipMalloc(&op->d_toff, sizeof(int) * toff.size()) == hipSuccess &&
               hipMalloc(&op->d_tw, sizeof(double) * tw.size()) == hipSuccess;
-    if (!ok) { op_free(op); return fail(HK_ENOMEM, "hipMalloc failed"); }
+    if (!ok) { live_take(op); op_free(op); return fail(HK_ENOMEM, "hipMalloc failed"); }
     ok = hipMemcpy(op->d_toff, toff.data(), sizeof(int) * toff.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(op->d_tw, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice) == hipSuccess;
-    if (!ok) { op_free(op); return fail(HK_EDEVICE, "hipMemcpy failed"); }
+    if (!ok) { live_take(op); op_free(op); return fail(HK_EDEVICE, "hipMemcpy failed"); }
+    live_add(op);
     *out = op;
     return HK_OK;
 }
@@ -816,6 +855,7 @@ hk_status hk_op_create_blur_psf(hk_context* ctx, int64_t ny, int64_t nx, const d
 hk_status hk_op_create_csr(hk_context* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
                            const int32_t* col, const void* val, hk_dtype dt, hk_op** out)
 {
+    HK_LIVE(ctx);
     if (!out) return fail(HK_EINVAL, "null output handle");
     *out = nullptr;
     if (!ctx || !rowptr || (nnz > 0 && (!col || !val))) return fail(HK_EINVAL, "null argument");
@@ -884,12 +924,14 @@ hk_status hk_op_create_csr(hk_context* ctx, int64_t m, int64_t n, int64_t nnz, c
              hipMemcpy(op->d_cit, cit.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) == hipSuccess &&
              hipMemcpy(op->d_cvt, cvt.data(), es * nnz, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) { op_free(op); return fail(HK_EDEVICE, "hipMemcpy failed for the CSR arrays"); }
+    live_add(op);
     *out = op;
     return HK_OK;
 }
 
 hk_status hk_op_shape(const hk_op* op, int64_t* m, int64_t* n)
 {
+    HK_LIVE(op);
     if (!op) return fail(HK_EINVAL, "null operator");
     if (m) *m = op->m;
     if (n) *n = op->n;
@@ -898,6 +940,7 @@ hk_status hk_op_shape(const hk_op* op, int64_t* m, int64_t* n)
 
 hk_status hk_op_apply(hk_op* op, int32_t transpose, const void* x_dev, void* y_dev)
 {
+    HK_LIVE(op);
     if (!op || !x_dev || !y_dev) return fail(HK_EINVAL, "null argument");
     if (transpose && op->kind != OP_CSR) return fail(HK_EUNSUPPORTED, "A^T products are provided for CSR operators");
     hk_status st = current_device(op->ctx);
@@ -958,7 +1001,7 @@ extern "C" {
 
 hk_status hk_op_destroy(hk_op* op)
 {
-    if (!op) return fail(HK_EINVAL, "null operator");
+    if (!live_take(op)) return fail(HK_EINVAL, op ? "unknown or destroyed operator" : "null operator");
     hipSetDevice(op->ctx->device);
     op_free(op);
     return HK_OK;
@@ -985,6 +1028,7 @@ static hk_status max_blocks(const hk_op* op, const hk_params* p, int rect, Plan*
 
 hk_status hk_solve_workspace_bytes(const hk_op* op, const hk_params* p_in, size_t* bytes)
 {
+    HK_LIVE(op);
     if (!bytes) return fail(HK_EINVAL, "null output");
     int rect = 0;
     hk_status st = validate(op, p_in, &rect);
@@ -1170,6 +1214,18 @@ static hk_status solve_bind(hk_solve* sv, hk_op* op, const hk_params* p, int rec
     return HK_OK;
 }
 
+// Frees a solve's events, its own workspace and the handle (no registry
+// check: also for a solve whose creation failed).
+static void solve_free(hk_solve* sv)
+{
+    hipSetDevice(sv->op->ctx->device);
+    for (int i = 0; i < hk_solve::NEV; ++i)
+        for (int q = 0; q < 3; ++q)
+            if (sv->ev[i][q]) hipEventDestroy(sv->ev[i][q]);
+    if (sv->own_ws) hipFree(sv->ws);
+    delete sv;
+}
+
 // Create a solve.  ws: a device buffer of at least the planned size to use
 // as workspace (zeroed on `stream`), or null to allocate one; nev: runs whose
 // timing events are kept; stream: where runs are ordered.
@@ -1201,20 +1257,21 @@ static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t
     for (int i = 0; i < sv->nev; ++i)
         for (int q = 0; q < 3; ++q)
             if (hipEventCreate(&sv->ev[i][q]) != hipSuccess) {
-                hk_solve_destroy(sv);
+                solve_free(sv);
                 return fail(HK_EDEVICE, "hipEventCreate failed");
             }
     // zero the workspace once (H, W, pivots read back even when unused)
     const hipError_t ze = sv->own_ws ? hipMemset(sv->ws, 0, w.total) : launch_fill_zero(sv->ws, w.total, stream);
     if (ze != hipSuccess) {
-        hk_solve_destroy(sv);
+        solve_free(sv);
         return fail(HK_EDEVICE, "zeroing the workspace failed");
     }
     st = solve_bind(sv, op, p, rect, pl, w, (unsigned char*)sv->ws, stream, true);
     if (st) {
-        hk_solve_destroy(sv);
+        solve_free(sv);
         return st;
     }
+    live_add(sv);
     *out = sv;
     return HK_OK;
 }
@@ -1265,6 +1322,7 @@ extern "C" {
 
 hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
 {
+    HK_LIVE(op);
     if (!op) return fail(HK_EINVAL, "null operator");
     return solve_create(op, p, nullptr, 0, hk_solve::NEV, op->ctx->stream, out);
 }
@@ -1272,6 +1330,7 @@ hk_status hk_solve_create(hk_op* op, const hk_params* p, hk_solve** out)
 hk_status hk_solve_create_with_workspace(hk_op* op, const hk_params* p, void* ws_dev, size_t ws_bytes,
                                          hk_solve** out)
 {
+    HK_LIVE(op);
     if (!op) return fail(HK_EINVAL, "null operator");
     if (ws_dev && ((uintptr_t)ws_dev & 255)) return fail(HK_EINVAL, "workspace pointer is not 256-byte aligned");
     if (ws_dev && ws_bytes == 0) return fail(HK_ENOMEM, "workspace of 0 bytes");
@@ -1280,6 +1339,7 @@ hk_status hk_solve_create_with_workspace(hk_op* op, const hk_params* p, void* ws
 
 hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
 {
+    HK_LIVE(sv);
     if (!sv || !b_dev || !x_dev) return fail(HK_EINVAL, "null argument");
     hk_status st = current_device(sv->op->ctx);
     if (st) return st;
@@ -1298,6 +1358,7 @@ hk_status hk_solve_run(hk_solve* sv, const void* b_dev, void* x_dev)
 
 hk_status hk_solve_run_noalloc(hk_op* op, const hk_params* p_in, const void* b_dev, void* x_dev, int32_t* info_dev)
 {
+    HK_LIVE(op);
     if (!op || !p_in || !b_dev || !x_dev) return fail(HK_EINVAL, "null argument");
     hk_context* ctx = op->ctx;
     int rect = 0;
@@ -1335,6 +1396,7 @@ hk_status hk_solve_run_noalloc(hk_op* op, const hk_params* p_in, const void* b_d
 
 hk_status hk_solve_wait(hk_solve* sv)
 {
+    HK_LIVE(sv);
     if (!sv) return fail(HK_EINVAL, "null solve");
     if (!sv->ran) return fail(HK_EINVAL, "the solve has not been run");
     if (sv->waited) return sv->last;
@@ -1375,6 +1437,7 @@ hk_status hk_solve_wait(hk_solve* sv)
 
 hk_status hk_solve_select_rhs(hk_solve* sv, int32_t rhs)
 {
+    HK_LIVE(sv);
     if (!sv) return fail(HK_EINVAL, "null solve");
     if (rhs < 0 || rhs >= sv->nrhs) return fail(HK_EINVAL, "right-hand side %d outside [0, %d)", rhs, sv->nrhs);
     sv->sel = rhs;
@@ -1399,6 +1462,7 @@ static hk_status ensure_done(hk_solve* sv)
 
 hk_status hk_solve_info(hk_solve* sv, int32_t* k_done)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (k_done) *k_done = sv->k_done;
@@ -1407,6 +1471,7 @@ hk_status hk_solve_info(hk_solve* sv, int32_t* k_done)
 
 hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     const int k = sv->prm.k;
@@ -1421,6 +1486,7 @@ hk_status hk_solve_get_hessenberg(hk_solve* sv, double* H, double* W)
 
 hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     const int k = sv->prm.k;
@@ -1440,6 +1506,7 @@ hk_status hk_solve_get_pivots(hk_solve* sv, int64_t* t, int64_t* g)
 
 hk_status hk_solve_get_residuals(hk_solve* sv, double* res)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (!res) return fail(HK_EINVAL, "null output");
@@ -1451,6 +1518,7 @@ hk_status hk_solve_get_residuals(hk_solve* sv, double* res)
 
 hk_status hk_solve_get_prefix_solution(hk_solve* sv, int32_t kp, void* x_dev)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (!x_dev) return fail(HK_EINVAL, "null output");
@@ -1475,6 +1543,7 @@ hk_status hk_solve_get_prefix_solution(hk_solve* sv, int32_t kp, void* x_dev)
 
 hk_status hk_solve_get_true_residuals(hk_solve* sv, double* res)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (!res) return fail(HK_EINVAL, "null output");
@@ -1529,6 +1598,7 @@ hk_status hk_solve_get_true_residuals(hk_solve* sv, double* res)
 
 hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     // the small problem's inputs (for the unsketched method H, [I; 0], beta e_1)
@@ -1543,6 +1613,7 @@ hk_status hk_solve_get_sketches(hk_solve* sv, double* Z, double* F, double* c)
 
 hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (!dst_dev) return fail(HK_EINVAL, "null output");
@@ -1571,6 +1642,7 @@ hk_status hk_solve_get_basis(hk_solve* sv, int32_t which, void* dst_dev)
 
 hk_status hk_solve_grid(const hk_solve* sv, int32_t* workgroups)
 {
+    HK_LIVE(sv);
     if (!sv || !workgroups) return fail(HK_EINVAL, "null argument");
     *workgroups = sv->G;
     return HK_OK;
@@ -1578,6 +1650,7 @@ hk_status hk_solve_grid(const hk_solve* sv, int32_t* workgroups)
 
 hk_status hk_solve_timing(hk_solve* sv, double* iterate_ms, double* total_ms)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     float a = 0.f, b = 0.f;
@@ -1591,6 +1664,7 @@ hk_status hk_solve_timing(hk_solve* sv, double* iterate_ms, double* total_ms)
 hk_status hk_solve_timing_history(hk_solve* sv, int32_t max_runs, double* iterate_ms,
                                   double* total_ms, int32_t* n)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (max_runs < 0 || !n) return fail(HK_EINVAL, "bad arguments");
@@ -1611,6 +1685,7 @@ hk_status hk_solve_timing_history(hk_solve* sv, int32_t max_runs, double* iterat
 
 hk_status hk_solve_get_trace(hk_solve* sv, int32_t max, uint64_t* ticks, int32_t* n, double* tick_ns)
 {
+    HK_LIVE(sv);
     hk_status st = ensure_done(sv);
     if (st) return st;
     if (!n || max < 0 || (max > 0 && !ticks)) return fail(HK_EINVAL, "bad arguments");
@@ -1629,13 +1704,8 @@ hk_status hk_solve_get_trace(hk_solve* sv, int32_t max, uint64_t* ticks, int32_t
 
 hk_status hk_solve_destroy(hk_solve* sv)
 {
-    if (!sv) return fail(HK_EINVAL, "null solve");
-    hipSetDevice(sv->op->ctx->device);
-    for (int i = 0; i < hk_solve::NEV; ++i)
-        for (int q = 0; q < 3; ++q)
-            if (sv->ev[i][q]) hipEventDestroy(sv->ev[i][q]);
-    if (sv->own_ws) hipFree(sv->ws);
-    delete sv;
+    if (!live_take(sv)) return fail(HK_EINVAL, sv ? "unknown or destroyed solve" : "null solve");
+    solve_free(sv);
     return HK_OK;
 }
 
@@ -1824,9 +1894,12 @@ hk_status server_pump(hk_server* s)
 
 extern "C" {
 
+static void server_free(hk_server* s);
+
 hk_status hk_server_create(hk_context* ctx, int32_t slots, size_t budget_bytes, int32_t workgroups,
                            hk_server** out)
 {
+    HK_LIVE(ctx);
     if (!ctx || !out) return fail(HK_EINVAL, "null argument");
     *out = nullptr;
     if (slots < 1 || slots > 16) return fail(HK_EINVAL, "slots = %d must be in [1, 16]", slots);
@@ -1847,16 +1920,25 @@ hk_status hk_server_create(hk_context* ctx, int32_t slots, size_t budget_bytes, 
     s->slots.resize((size_t)slots);
     for (auto& sl : s->slots)
         if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess) {
-            hk_server_destroy(s);
+            server_free(s);
             return fail(HK_EDEVICE, "hipStreamCreateWithFlags failed");
         }
+    live_add(s);
     *out = s;
     return HK_OK;
 }
 
 hk_status hk_server_destroy(hk_server* s)
 {
-    if (!s) return fail(HK_EINVAL, "null server");
+    if (!live_take(s)) return fail(HK_EINVAL, s ? "unknown or destroyed server" : "null server");
+    server_free(s);
+    return HK_OK;
+}
+
+// Waits for the running solves and frees everything the server holds (no
+// registry check: also for a server whose creation failed).
+static void server_free(hk_server* s)
+{
     hipSetDevice(s->ctx->device);
     for (auto& sl : s->slots) {
         if (sl.st) hipStreamSynchronize(sl.st);
@@ -1868,12 +1950,13 @@ hk_status hk_server_destroy(hk_server* s)
     for (auto& rq : s->queue) hipEventDestroy(rq.ready);
     for (hipEvent_t e : s->evpool) hipEventDestroy(e);
     delete s;
-    return HK_OK;
 }
 
 hk_status hk_server_submit(hk_server* s, hk_op* op, const hk_params* params, const void* b_dev, void* x_dev,
                            int64_t* ticket)
 {
+    HK_LIVE(s);
+    HK_LIVE(op);
     if (!s || !op || !params || !b_dev || !x_dev || !ticket) return fail(HK_EINVAL, "null argument");
     if (op->ctx->device != s->ctx->device) return fail(HK_EINVAL, "the operator lives on another device");
     hk_status st = current_device(s->ctx);
@@ -1900,6 +1983,7 @@ hk_status hk_server_submit(hk_server* s, hk_op* op, const hk_params* params, con
 
 hk_status hk_server_poll(hk_server* s, int64_t* completed)
 {
+    HK_LIVE(s);
     if (!s) return fail(HK_EINVAL, "null server");
     hk_status st = current_device(s->ctx);
     if (st) return st;
@@ -1910,6 +1994,7 @@ hk_status hk_server_poll(hk_server* s, int64_t* completed)
 
 hk_status hk_server_wait(hk_server* s, int64_t ticket)
 {
+    HK_LIVE(s);
     if (!s || ticket < 0 || ticket >= (int64_t)s->res.size()) return fail(HK_EINVAL, "bad ticket");
     hk_status st = current_device(s->ctx);
     if (st) return st;
@@ -1927,6 +2012,7 @@ hk_status hk_server_wait(hk_server* s, int64_t ticket)
 hk_status hk_server_result(hk_server* s, int64_t ticket, hk_status* status, int32_t* k_done, int32_t* workgroups,
                            double* t_submit, double* t_start, double* t_finish)
 {
+    HK_LIVE(s);
     if (!s || ticket < 0 || ticket >= (int64_t)s->res.size()) return fail(HK_EINVAL, "bad ticket");
     const auto& r = s->res[(size_t)ticket];
     if (!r.done) return fail(HK_EINVAL, "request %lld has not finished", (long long)ticket);

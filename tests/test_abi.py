@@ -60,6 +60,22 @@ def test_version_and_null_argument_errors(hk):
     assert L.hk_server_result(None, 0, None, None, None, None, None, None) == hk.HK_EINVAL
 
 
+def test_unknown_handles_are_refused_without_use(hk):
+    """A handle the library did not create (or has destroyed) is refused with
+    HK_EINVAL before its memory is read: the address below is never mapped
+    as a handle."""
+    import ctypes as C
+    L = hk.lib()
+    bogus = C.c_void_p(0x10)
+    assert L.hk_solve_wait(bogus) == hk.HK_EINVAL
+    assert "unknown or destroyed" in hk.hk_last_error()
+    assert L.hk_solve_destroy(bogus) == hk.HK_EINVAL
+    assert L.hk_op_destroy(bogus) == hk.HK_EINVAL
+    assert L.hk_context_destroy(bogus) == hk.HK_EINVAL
+    assert L.hk_server_destroy(bogus) == hk.HK_EINVAL
+    assert L.hk_server_poll(bogus, None) == hk.HK_EINVAL
+
+
 def test_params_struct_layout(hk, tmp_path):
     """The ctypes mirror of hk_params matches the C header, as compiled by gcc."""
     import subprocess
