@@ -97,7 +97,12 @@ typedef struct hk_op hk_op;
 typedef struct hk_solve hk_solve;
 typedef struct hk_server hk_server;
 
-/* ABI version (HK_ABI_VERSION) and the thread-local last error message. */
+/* ABI version (HK_ABI_VERSION) and the thread-local last error message.
+ * Logging: the environment variable HK_LOG, read once per process, selects
+ * 0 (unset: silent), 1 (every refused call and failure is also written to
+ * stderr as "hk: status <code>: <message>") or 2 (as 1, plus one line per
+ * solve plan: kernel, workgroups, tiles, LDS and workspace bytes, and one
+ * per server admission). */
 int32_t hk_abi_version(void);
 const char* hk_last_error(void);
 

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -27,6 +28,18 @@ namespace {
 
 thread_local std::string g_err;
 
+// HK_LOG (environment, read once): 0 or unset: silent; 1: every refused call
+// and failure is also written to stderr; 2: as 1, plus one line per solve
+// plan (kernel, grid, tile, LDS, workspace) and per server admission.
+int log_level()
+{
+    static const int lv = [] {
+        const char* e = std::getenv("HK_LOG");
+        return e ? std::atoi(e) : 0;
+    }();
+    return lv;
+}
+
 hk_status fail(hk_status st, const char* fmt, ...)
 {
     char buf[512];
@@ -35,7 +48,19 @@ hk_status fail(hk_status st, const char* fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    if (log_level() >= 1) std::fprintf(stderr, "hk: status %d: %s\n", (int)st, buf);
     return st;
+}
+
+void log_info(const char* fmt, ...)
+{
+    if (log_level() < 2) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "hk: %s\n", buf);
 }
 
 // Live handles: every context, operator, solve and server from its creation
@@ -1271,6 +1296,18 @@ static hk_status solve_create(hk_op* op, const hk_params* p_in, void* ws, size_t
         solve_free(sv);
         return st;
     }
+    {
+        static const char* kname[] = {"blur (generic)", "csr (generic)", "blur (single barrier)"};
+        char tile[64];
+        if (pl.kernel == OP_CSR)
+            std::snprintf(tile, sizeof tile, "about %lld rows", (long long)((op->m + pl.G - 1) / pl.G));
+        else
+            std::snprintf(tile, sizeof tile, "%dx%d pixels", pl.spm.TY, pl.spm.TX);
+        log_info("solve: %s kernel, %d workgroups, tiles of %s, %d elements per thread, LDS %d B, "
+                 "workspace %zu B, k = %d, s = %d, %d right-hand side(s), least squares on %d workgroup(s)",
+                 kname[pl.kernel], pl.G, tile, pl.ept, pl.lds_total, w.total, p->k, p->s,
+                 std::max(1, p->nrhs), std::max(1, sv->la.nwg));
+    }
     live_add(sv);
     *out = sv;
     return HK_OK;
@@ -1877,6 +1914,8 @@ hk_status server_pump(hk_server* s)
             finish_request(s, rq.ticket, st, 0);
             continue;
         }
+        log_info("server: request %lld admitted on slot %d, %d workgroups, %zu B of workspace",
+                 (long long)rq.ticket, (int)(slot - s->slots.data()), sv->G, cap);
         slot->sv = sv;
         slot->ticket = rq.ticket;
         slot->buf = buf;

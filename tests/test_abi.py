@@ -76,6 +76,21 @@ def test_unknown_handles_are_refused_without_use(hk):
     assert L.hk_server_poll(bogus, None) == hk.HK_EINVAL
 
 
+def test_log_level_one_reports_refused_calls(hk):
+    """HK_LOG=1: a refused call is also written to stderr (the level is read
+    once per process, so this runs in a child)."""
+    import subprocess
+    import sys
+    code = "import paper_2502_02721_amd as hk; hk.lib().hk_solve_wait(None)"
+    env = dict(os.environ, HK_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "hk: status -1: null handle sv" in r.stderr
+    env["HK_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert "hk:" not in r.stderr
+
+
 def test_params_struct_layout(hk, tmp_path):
     """The ctypes mirror of hk_params matches the C header, as compiled by gcc."""
     import subprocess
