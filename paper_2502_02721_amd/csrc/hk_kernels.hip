@@ -129,10 +129,14 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a)
     const int st = ctl->status;
     int kd = (st < 0) ? 0 : ctl->k_done;
     if (a.kcap > 0) kd = min(kd, a.kcap);
+    // unrolled so that the loads of 16 columns are in flight together; the
+    // FMAs still run in increasing j
     double acc = 0.0;
     if (scale) {
+#pragma unroll 16
         for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], y[j] * scale[j], acc);
     } else {
+#pragma unroll 16
         for (int j = 0; j < kd; ++j) acc = fma((double)L[(long long)j * a.ldl + i], y[j], acc);
     }
     x[i] = (TO)acc;
