@@ -656,15 +656,32 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
     }
     if (wg != 0) return;       // the substitution and the history: the first workgroup
     // ---- residual history and back substitution R y = d (d and the
-    // reciprocals of R's diagonal staged in LDS)
-    double* dl = W;                                // kd, overwritten by the substitution
-    double* rd = W + kd;                           // kd
-    double* d2 = W + 2 * kd;                       // kd, read by the residual loop
+    // reciprocals of R's diagonal staged in LDS).  The panels are done, so
+    // this workgroup's LDS is free: when the strict upper triangle of R
+    // (packed by columns, column c holding rows 0 .. c-1 from c(c-1)/2) fits
+    // in it beside d, it is staged there as well and the substitution reads
+    // R from LDS instead of global memory.
+    const size_t lds_dbl = (size_t)NB * RP + 2 * (size_t)(k + 1) * NB + (size_t)LSB_NW * 256 + 4 * 256 + 32;
+    const size_t npk = (size_t)kd * (kd - 1) / 2;
+    const bool staged = npk + 3 * (size_t)kd <= lds_dbl;
+    double* Rp = staged ? (double*)smem : nullptr;
+    double* dl = staged ? (double*)smem + npk : W;     // kd, overwritten by the substitution
+    double* rd = dl + kd;                              // kd
+    double* d2 = dl + 2 * kd;                          // kd, read by the residual loop
     for (int i = threadIdx.x; i < kd; i += LSB_NT) {
         const double di = dv[i];
         dl[i] = di;
         d2[i] = di;
         rd[i] = 1.0 / Rm[(long long)i * k + i];
+    }
+    if (staged) {
+        for (size_t e = threadIdx.x; e < npk; e += LSB_NT) {
+            int c = (int)((1.0 + sqrt(1.0 + 8.0 * (double)e)) * 0.5);   // column of packed entry e
+            while ((size_t)c * (c - 1) / 2 > e) --c;
+            while ((size_t)(c + 1) * c / 2 <= e) ++c;
+            const int q = (int)(e - (size_t)c * (c - 1) / 2);
+            Rp[e] = Rm[(long long)c * k + q];
+        }
     }
     __syncthreads();
     if (threadIdx.x == 64) {                       // wave 1, beside the substitution
@@ -674,7 +691,52 @@ __global__ __launch_bounds__(LSB_NT) void small_ls_blocked_kernel(LsArgs a_in)
             acc += d2[j] * d2[j];
         }
     }
-    if (threadIdx.x < 64) {
+    if (threadIdx.x < 64 && staged) {
+        // column-oriented as below, with d and the reciprocals in registers
+        // (row q = lane + 64 u in slot u) and y_i formed from lane i & 63 by
+        // readlane: y_i = d_i (1 / R(i, i)), then d_q = fma(-R(q, i), y_i, d_q)
+        // for q < i, the same operations in the same order.  The LDS column
+        // of the next RING steps is read ahead.
+        constexpr int RING = 4;
+        const int lane = threadIdx.x;
+        double dr[4], rr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = lane + 64 * u;
+            dr[u] = q < kd ? dl[q] : 0.0;
+            rr[u] = q < kd ? rd[q] : 0.0;
+        }
+        double ring[RING][4];
+        auto load = [&](int i, double (&dst)[4]) {
+            const int c = max(i, 1);
+            const double* col = Rp + (size_t)c * (c - 1) / 2;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[u] = col[min(lane + 64 * u, c - 1)];   // rows >= c masked at use
+        };
+#pragma unroll
+        for (int r = 0; r < RING; ++r) load(kd - 1 - r, ring[r]);
+        for (int i0 = kd - 1; i0 >= 0; i0 -= RING) {
+#pragma unroll
+            for (int r = 0; r < RING; ++r) {
+                const int i = i0 - r;
+                if (i >= 0) {
+                    const int ui = i >> 6, li = i & 63;
+                    double ds = dr[0], rs = rr[0];
+#pragma unroll
+                    for (int u = 1; u < 4; ++u)
+                        if (ui == u) { ds = dr[u]; rs = rr[u]; }
+                    const double yi = readlane_d(ds, li) * readlane_d(rs, li);
+                    if (lane == 0) a.y[i] = yi;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int q = lane + 64 * u;
+                        if (q < i) dr[u] = fma(-ring[r][u], yi, dr[u]);
+                    }
+                }
+                load(i - RING, ring[r]);
+            }
+        }
+    } else if (threadIdx.x < 64) {
         // column-oriented: y_i final, then d_q -= R(q, i) y_i for q < i; the
         // R column of the next RING steps is in flight meanwhile
         constexpr int RING = 4;
