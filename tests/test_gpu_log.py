@@ -38,5 +38,6 @@ def test_log_level_two_reports_plans_and_admissions():
     assert r.returncode == 0, r.stderr[-3000:]
     assert "status 0" in r.stdout and "server 0" in r.stdout
     assert "hk: solve: blur (single barrier) kernel" in r.stderr
-    assert "tiles of 8x8 pixels" in r.stderr or "tiles of" in r.stderr
+    # 4096 pixels over at most one workgroup per compute unit: 64 tiles of 8 x 8
+    assert "64 workgroups, tiles of 8x8 pixels" in r.stderr
     assert "hk: server: request 0 admitted on slot 0" in r.stderr
